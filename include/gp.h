@@ -1,0 +1,129 @@
+/*
+ * gp.h - C ABI of the MI355X (gfx950) two-way task-DAG partitioner.
+ *
+ * Splits the kernels of a weighted data-flow task graph between a CPU memory
+ * node (part 0) and a GPU memory node (part 1), the graph-partition
+ * scheduling policy of Wu, Lohmann and Schroeder-Preikschat (Section III-B):
+ *   - vertex weight = cost of a kernel on a processor (two costs per vertex:
+ *     CPU and GPU), edge weight = cost (bytes) of the transfer a dependency
+ *     implies; a transfer costs the same in both directions, so the graph is
+ *     undirected;
+ *   - the target share of each processor follows Eq. (1)-(2),
+ *     R_CPU = T_GPU / (T_GPU + T_CPU), R_GPU = 1 - R_CPU, given here as an
+ *     integer ratio r0:r1 with an imbalance tolerance eps;
+ *   - k = 2 parts; every kernel is pinned to exactly one processor;
+ *   - the objective keeps the load balanced while cutting as little edge
+ *     weight as possible (Section IV-C).
+ * The partition itself is a deterministic multilevel method (heavy-edge
+ * matching, contraction, greedy-growing initial bisection, prefix-admission
+ * boundary refinement).  All of its arithmetic is integer, so the result is
+ * one exact assignment per (graph, options); it does not depend on the GPU's
+ * scheduling of threads.
+ *
+ * Graph layout (CSR, the adjacency form the paper hands its partitioner):
+ *   xadj   int32[n+1]  row offsets, xadj[0] = 0, non-decreasing, 2m = xadj[n] < 2^31
+ *   adjncy int32[2m]   neighbour ids in [0, n); every edge appears in both rows
+ *   adjwgt int64[2m]   edge weights >= 0, equal in both directions
+ *   vwgt   int64[n][2] per vertex (cpu cost, gpu cost) >= 0
+ * Sums of adjwgt and of each vwgt column must stay below 2^62.
+ *
+ * Threads: a gp_graph handle is used by one host thread at a time.
+ * Errors: no call throws; on error nothing is written to the outputs.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_graph gp_graph;
+
+typedef enum {
+  GP_OK = 0,
+  GP_EINVAL = 1,     /* bad argument, bad option or malformed xadj */
+  GP_EASYM = 2,      /* an edge u-v without v-u of equal weight */
+  GP_EDUP = 3,       /* a neighbour listed twice in one row */
+  GP_ESELF = 4,      /* a self loop */
+  GP_ERANGE = 5,     /* a neighbour id outside [0, n) or a negative weight */
+  GP_EOVERFLOW = 6,  /* sum of edge weights or of a cost column >= 2^62 */
+  GP_ENOMEM = 7,     /* device or host allocation failed */
+  GP_EDEVICE = 8,    /* a HIP runtime call failed */
+  GP_EMODEL = 9      /* GP_LEARNED without a usable model */
+} gp_status;
+
+/* flags for gp_create (GP_HOST_PTRS) and gp_options.flags (the others) */
+enum {
+  GP_HOST_PTRS = 1,  /* input / output pointers are host memory (else device memory) */
+  GP_LEARNED = 2,    /* run the learned coarsest-level proposal beside the plain one */
+  GP_TRACE = 4       /* record per-level statistics (costs one extra pass per level) */
+};
+
+typedef struct {
+  int64_t ratio[2];      /* CPU : GPU target shares, Eq. (1)-(2); each in [0, 2^40), sum > 0 */
+  int32_t eps_ppm;       /* imbalance tolerance in parts per million, [0, 10^6]; 30000 = 3 % */
+  int32_t balance_on;    /* 0: balance the CPU-cost column (default), 1: the GPU-cost column */
+  uint64_t seed;         /* seed of the matching tie-break hash */
+  int32_t coarsen_to;    /* coarsen while n > coarsen_to (>= 1; default 2048) */
+  int32_t match_rounds;  /* proposal rounds per level, [0, 64] (default 8) */
+  int32_t refine_passes; /* refinement passes per level, [0, 64] (default 8) */
+  int32_t init_trials;   /* greedy-growing trials, [1, 64] (default 16) */
+  int32_t flags;         /* GP_LEARNED | GP_TRACE | GP_HOST_PTRS (for part/res of batch calls) */
+  int32_t reserved;
+  const void* model;     /* from gp_model_create; required iff GP_LEARNED */
+} gp_options;
+
+typedef struct {
+  int64_t cut;           /* sum of w over edges whose ends lie in different parts */
+  int64_t load[2];       /* balance-column weight of part 0 and part 1 */
+  int64_t time[2];       /* sum of cpu costs of part 0, sum of gpu costs of part 1 */
+  int32_t feasible;      /* load[p] <= maxw[p] for both parts */
+  int32_t levels;        /* number of coarse graphs built */
+  int32_t used_learned;  /* 1 when the learned proposal beat the plain one */
+  int32_t reserved;
+} gp_result;
+
+/* Fill *o with the defaults: ratio 1:4, eps 3 %, CPU column, seed 0, 2048, 8, 8, 16. */
+void gp_options_default(gp_options* o);
+
+/* Eq. (1)-(2) as an integer ratio: R_CPU = T_GPU/(T_GPU+T_CPU), so
+ * ratio = {t_gpu, t_cpu} divided by their gcd.  t >= 0, not both 0. */
+gp_status gp_ratio_from_times(int64_t t_cpu, int64_t t_gpu, int64_t ratio[2]);
+
+/* Check the graph and copy it into library-owned device memory in canonical
+ * form (rows sorted by neighbour).  The inputs are read only during the call
+ * and may be freed afterwards.  flags: GP_HOST_PTRS when the arrays are host
+ * memory.  stream: the hipStream_t all work of this handle runs on (NULL =
+ * the default stream).  Returns GP_EINVAL, GP_ERANGE, GP_ESELF, GP_EDUP,
+ * GP_EASYM or GP_EOVERFLOW, checked in that order of precedence, for a
+ * malformed graph; *g is then left NULL. */
+gp_status gp_create(gp_graph** g, int32_t n, const int32_t* xadj, const int32_t* adjncy,
+                    const int64_t* adjwgt, const int64_t* vwgt, int32_t flags, void* stream);
+
+/* Change the stream of a handle. */
+gp_status gp_set_stream(gp_graph* g, void* stream);
+
+/* Partition.  part: caller-owned int8[n] receiving 0 (CPU) or 1 (GPU) per
+ * vertex, in the caller's vertex order; device memory unless the handle was
+ * created with GP_HOST_PTRS.  res: host memory.  The call returns after the
+ * result is complete.  An infeasible balance is not an error: the call
+ * returns GP_OK with res->feasible = 0 and the best assignment found. */
+gp_status gp_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res);
+
+/* As gp_partition, also writing 8 int64 per level (level 0 first, at most
+ * trace_cap levels, host memory): n, 2m, refinement passes, vertices moved,
+ * cut after refinement, load[0], load[1], pairs matched on that level. */
+gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
+                             int64_t* trace, int32_t trace_cap);
+
+void gp_destroy(gp_graph* g);
+
+const char* gp_strerror(gp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

@@ -45,7 +45,9 @@ def _load():
     lib.or_edge_hash.restype = u64
     lib.or_edge_hash.argtypes = [u64, i32, i32, i32]
     lib.or_match.restype = i64
-    lib.or_match.argtypes = [i32, vp, vp, vp, vp, i64, u64, i32, i32, vp]
+    lib.or_match.argtypes = [i32, vp, vp, vp, vp, i64, u64, i32, i32, i32, vp]
+    lib.or_match_twohop.restype = i64
+    lib.or_match_twohop.argtypes = [i32, vp, vp, vp, vp, i64, u64, i32, vp]
     lib.or_contract.restype = i32
     lib.or_contract.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.or_cut.restype = i64
@@ -129,12 +131,22 @@ def edge_hash(seed: int, level: int, a: int, b: int) -> int:
     return int(_load().or_edge_hash(seed, level, a, b))
 
 
-def match(n, xadj, adjncy, adjwgt, b, cap, seed, level, rounds):
+def match(n, xadj, adjncy, adjwgt, b, cap, seed, level, rounds, twohop=True):
+    """R proposal rounds, then (twohop) the two-hop pairing pass."""
     xadj, adjncy, adjwgt, b = (_c(xadj, np.int32), _c(adjncy, np.int32), _c(adjwgt, np.int64),
                                _c(b, np.int64))
     m = np.zeros(max(n, 1), np.int32)
     pairs = _load().or_match(n, _p(xadj), _p(adjncy), _p(adjwgt), _p(b), cap, seed, level,
-                             rounds, _p(m))
+                             rounds, int(bool(twohop)), _p(m))
+    return int(pairs), m[:n]
+
+
+def match_twohop(n, xadj, adjncy, adjwgt, b, cap, seed, level, matchv):
+    """The two-hop pairing pass alone, applied to a given matching."""
+    m = _c(matchv, np.int32).copy()
+    pairs = _load().or_match_twohop(n, _p(_c(xadj, np.int32)), _p(_c(adjncy, np.int32)),
+                                    _p(_c(adjwgt, np.int64)), _p(_c(b, np.int64)), cap, seed,
+                                    level, _p(m))
     return int(pairs), m[:n]
 
 

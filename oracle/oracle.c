@@ -200,9 +200,9 @@ static int edge_before(int64_t w1, uint64_t h1, int32_t lo1, int32_t hi1, int64_
   return hi1 < hi2;
 }
 
-int64_t or_match(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
-                 const int64_t* b, int64_t cap, uint64_t seed, int32_t level, int32_t R,
-                 int32_t* match) {
+int64_t or_match_rounds(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                        const int64_t* b, int64_t cap, uint64_t seed, int32_t level, int32_t R,
+                        int32_t* match) {
   int32_t* prop = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   if (!prop) return -1;
   for (int32_t u = 0; u < n; u++) match[u] = -1;
@@ -237,6 +237,74 @@ int64_t or_match(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
   }
   free(prop);
   return pairs;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-hop pass, after the rounds.  An unmatched vertex u with neighbours    */
+/* has a hub: its first neighbour under the edge order, whether or not that */
+/* neighbour is matched.  Unmatched vertices with the same hub h, taken in   */
+/* ascending id, are paired first-second, third-fourth, ... ; the unmatched  */
+/* vertices without neighbours form one more group, also in ascending id.   */
+/* A pair is formed only when b(x) + b(y) <= cap; otherwise both stay       */
+/* single.  Pairs share a neighbour (or have none), so every group is a set */
+/* of leaves around one vertex, the structure that stalls plain matching.   */
+/* Returns the number of pairs formed.                                      */
+/* ------------------------------------------------------------------------ */
+int64_t or_match_twohop(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                        const int64_t* b, int64_t cap, uint64_t seed, int32_t level,
+                        int32_t* match) {
+  int32_t* hub = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* grp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!hub || !grp) { free(hub); free(grp); return -1; }
+  for (int32_t u = 0; u < n; u++) {
+    hub[u] = -1;
+    if (match[u] != -1) continue;
+    int64_t bw = 0;
+    uint64_t bh = 0;
+    int32_t blo = 0, bhi = 0;
+    for (int32_t e = xadj[u]; e < xadj[u + 1]; e++) {
+      int32_t v = adj[e];
+      int32_t lo = u < v ? u : v, hi = u < v ? v : u;
+      uint64_t h = or_edge_hash(seed, level, lo, hi);
+      if (hub[u] < 0 || edge_before(w[e], h, lo, hi, bw, bh, blo, bhi)) {
+        hub[u] = v; bw = w[e]; bh = h; blo = lo; bhi = hi;
+      }
+    }
+  }
+  int64_t pairs = 0;
+  /* groups around each hub h: the unmatched vertices of row h whose hub is h */
+  for (int32_t h = 0; h < n; h++) {
+    int32_t k = 0;
+    for (int32_t e = xadj[h]; e < xadj[h + 1]; e++) {
+      int32_t x = adj[e];
+      if (match[x] == -1 && hub[x] == h) grp[k++] = x;
+    }
+    for (int32_t i = 0; i + 1 < k; i += 2) {
+      int32_t x = grp[i], y = grp[i + 1];
+      if (b[x] + b[y] <= cap) { match[x] = y; match[y] = x; pairs++; }
+    }
+  }
+  /* vertices without neighbours */
+  int32_t k = 0;
+  for (int32_t u = 0; u < n; u++)
+    if (match[u] == -1 && xadj[u + 1] == xadj[u]) grp[k++] = u;
+  for (int32_t i = 0; i + 1 < k; i += 2) {
+    int32_t x = grp[i], y = grp[i + 1];
+    if (b[x] + b[y] <= cap) { match[x] = y; match[y] = x; pairs++; }
+  }
+  free(hub);
+  free(grp);
+  return pairs;
+}
+
+/* R proposal rounds, then the two-hop pass (when twohop != 0) */
+int64_t or_match(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                 const int64_t* b, int64_t cap, uint64_t seed, int32_t level, int32_t R,
+                 int32_t twohop, int32_t* match) {
+  int64_t p1 = or_match_rounds(n, xadj, adj, w, b, cap, seed, level, R, match);
+  if (p1 < 0 || !twohop) return p1;
+  int64_t p2 = or_match_twohop(n, xadj, adj, w, b, cap, seed, level, match);
+  return p2 < 0 ? -1 : p1 + p2;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -617,7 +685,7 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
     int32_t* match = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->n);
     cmap[L] = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->n);
     if (!match || !cmap[L]) { free(match); rc = OR_ENOMEM; break; }
-    pairs[L] = or_match(g->n, g->xadj, g->adj, g->w, b, cap, seed, L, (int32_t)R, match);
+    pairs[L] = or_match(g->n, g->xadj, g->adj, g->w, b, cap, seed, L, (int32_t)R, 1, match);
     if (pairs[L] < 0 || or_contract_og(g, match, cmap[L], &lv[L + 1]) != OR_OK) {
       free(match); rc = OR_ENOMEM; break;
     }

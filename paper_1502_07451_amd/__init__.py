@@ -1,0 +1,213 @@
+"""Python binding of libgp.so, the gfx950 two-way task-DAG partitioner.
+
+Argument marshalling only: every step of the partition runs in the HIP
+kernels of ``libgp.so``.  PyTorch supplies device memory and the current HIP
+stream.  The library must be built first (``python
+paper_1502_07451_amd/build.py`` or ``__graft_entry__.build()``); importing the
+binding without it raises ImportError.
+
+Names follow the C ABI in ``include/gp.h``: ``create`` wraps ``gp_create``,
+``Graph.partition`` wraps ``gp_partition`` / ``gp_partition_trace``,
+``ratio_from_times`` wraps ``gp_ratio_from_times`` (Eq. (1)-(2)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgp.so")
+
+OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)
+HOST_PTRS, LEARNED, TRACE = 1, 2, 4
+
+
+class GPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: status {status} ({strerror(status)})")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("ratio", ctypes.c_int64 * 2), ("eps_ppm", ctypes.c_int32),
+                ("balance_on", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("coarsen_to", ctypes.c_int32), ("match_rounds", ctypes.c_int32),
+                ("refine_passes", ctypes.c_int32), ("init_trials", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("model", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("load", ctypes.c_int64 * 2),
+                ("time", ctypes.c_int64 * 2), ("feasible", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("used_learned", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return dict(cut=self.cut, load=(self.load[0], self.load[1]),
+                    time=(self.time[0], self.time[1]), feasible=self.feasible,
+                    levels=self.levels, used_learned=self.used_learned)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python paper_1502_07451_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.gp_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.gp_options_default.restype = None
+    lib.gp_ratio_from_times.argtypes = [i64, i64, vp]
+    lib.gp_ratio_from_times.restype = ctypes.c_int
+    lib.gp_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, vp, i32, vp]
+    lib.gp_create.restype = ctypes.c_int
+    lib.gp_set_stream.argtypes = [vp, vp]
+    lib.gp_set_stream.restype = ctypes.c_int
+    lib.gp_partition.argtypes = [vp, ctypes.POINTER(Options), vp, ctypes.POINTER(Result)]
+    lib.gp_partition.restype = ctypes.c_int
+    lib.gp_partition_trace.argtypes = [vp, ctypes.POINTER(Options), vp, ctypes.POINTER(Result),
+                                       vp, i32]
+    lib.gp_partition_trace.restype = ctypes.c_int
+    lib.gp_destroy.argtypes = [vp]
+    lib.gp_destroy.restype = None
+    lib.gp_strerror.argtypes = [ctypes.c_int]
+    lib.gp_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ["gp_options_default", "gp_ratio_from_times", "gp_create", "gp_set_stream",
+            "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror"]
+
+
+def strerror(status: int) -> str:
+    return _lib.gp_strerror(status).decode()
+
+
+def options(ratio=(1, 4), eps_ppm=30000, balance_on=0, seed=0, coarsen_to=2048, match_rounds=8,
+            refine_passes=8, init_trials=16, flags=0, model=None) -> Options:
+    o = Options()
+    _lib.gp_options_default(ctypes.byref(o))
+    o.ratio[0], o.ratio[1] = int(ratio[0]), int(ratio[1])
+    o.eps_ppm, o.balance_on = int(eps_ppm), int(balance_on)
+    o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.coarsen_to, o.match_rounds = int(coarsen_to), int(match_rounds)
+    o.refine_passes, o.init_trials = int(refine_passes), int(init_trials)
+    o.flags = int(flags)
+    o.model = model
+    return o
+
+
+def ratio_from_times(t_cpu: int, t_gpu: int):
+    out = (ctypes.c_int64 * 2)()
+    st = _lib.gp_ratio_from_times(int(t_cpu), int(t_gpu), out)
+    return st, (out[0], out[1])
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor, host pointer of a numpy array."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+class Graph:
+    """A library-owned copy of one graph (gp_create); reuse it for many partitions."""
+
+    def __init__(self, n, xadj, adjncy, adjwgt, vwgt, stream=None):
+        import torch
+        self.n = int(n)
+        self.host = isinstance(xadj, np.ndarray)
+        arrays = (xadj, adjncy, adjwgt, vwgt)
+        want = (np.int32, np.int32, np.int64, np.int64)
+        tw = (torch.int32, torch.int32, torch.int64, torch.int64)
+        for a, dn, dt in zip(arrays, want, tw):
+            if self.host:
+                if a.dtype != dn or not a.flags["C_CONTIGUOUS"]:
+                    raise TypeError("host arrays must be contiguous int32/int32/int64/int64")
+            elif a.dtype != dt or not a.is_contiguous() or not a.is_cuda:
+                raise TypeError("device tensors must be contiguous cuda int32/int32/int64/int64")
+        self.device = None if self.host else xadj.device
+        self.stream = stream if stream is not None else (None if self.host else _current_stream())
+        h = ctypes.c_void_p()
+        st = _lib.gp_create(ctypes.byref(h), self.n, *(_ptr(a) for a in arrays),
+                            HOST_PTRS if self.host else 0, self.stream)
+        if st != OK:
+            raise GPError(st, "gp_create")
+        self._h = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        st = _lib.gp_set_stream(self._h, stream)
+        if st != OK:
+            raise GPError(st, "gp_set_stream")
+
+    def partition(self, opts: Options | None = None, part=None, trace_cap: int = 0):
+        """Returns (part, Result[, trace]) - part is int8[n]: 0 = CPU, 1 = GPU."""
+        import torch
+        opts = opts or options()
+        if part is None:
+            if self.host:
+                part = np.zeros(max(self.n, 1), np.int8)
+            else:
+                part = torch.empty(max(self.n, 1), dtype=torch.int8, device=self.device)
+        res = Result()
+        if trace_cap > 0:
+            tr = np.zeros(8 * trace_cap, np.int64)
+            st = _lib.gp_partition_trace(self._h, ctypes.byref(opts), _ptr(part),
+                                         ctypes.byref(res), _ptr(tr), trace_cap)
+        else:
+            st = _lib.gp_partition(self._h, ctypes.byref(opts), _ptr(part), ctypes.byref(res))
+        if st != OK:
+            raise GPError(st, "gp_partition")
+        part = part[:self.n]
+        if trace_cap > 0:
+            return part, res, tr.reshape(trace_cap, 8)[:res.levels + 1].copy()
+        return part, res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_status(n, xadj, adjncy, adjwgt, vwgt, host: bool) -> int:
+    """gp_create's status for the given arrays (the handle is destroyed again)."""
+    h = ctypes.c_void_p()
+    st = _lib.gp_create(ctypes.byref(h), int(n), _ptr(xadj), _ptr(adjncy), _ptr(adjwgt),
+                        _ptr(vwgt), HOST_PTRS if host else 0,
+                        None if host else _current_stream())
+    if st == OK:
+        _lib.gp_destroy(h)
+    return st
+
+
+def to_device(g, device="cuda"):
+    """Copies a graph given as numpy arrays (n, xadj, adjncy, adjwgt, vwgt) to device tensors."""
+    import torch
+    vw = np.ascontiguousarray(g.vwgt, dtype=np.int64).reshape(-1)
+    return (g.n, torch.from_numpy(np.ascontiguousarray(g.xadj, np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(g.adjncy, np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(g.adjwgt, np.int64)).to(device),
+            torch.from_numpy(vw).to(device))
+
+
+def create(g, device="cuda", stream=None) -> Graph:
+    """gp_create from an object with n, xadj, adjncy, adjwgt, vwgt (numpy) on a device."""
+    return Graph(*to_device(g, device), stream=stream)

@@ -1,0 +1,405 @@
+// gp_dev.h - device building blocks for gfx950 (wave64).
+//
+// Teams: a team is TW consecutive lanes of one wave (TW in 1..64) that work
+// on one CSR row; reductions inside a team use cross-lane shuffles.  Block
+// reductions combine per-wave results through LDS.  Everything here is
+// integer arithmetic, so results do not depend on the order in which lanes,
+// waves or blocks combine.
+#pragma once
+
+#include <limits.h>
+
+#include "gp_internal.h"
+
+namespace gpk {
+
+typedef unsigned __int128 u128;
+
+// SplitMix64 output finaliser (Steele, Lea, Flood 2014; constants by Vigna).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// ----------------------------------------------------------------- teams
+template <int TW, class T>
+__device__ __forceinline__ T team_sum(T v) {
+#pragma unroll
+  for (int o = TW / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TW);
+  return v;
+}
+
+template <int TW, class T>
+__device__ __forceinline__ T team_max(T v) {
+#pragma unroll
+  for (int o = TW / 2; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, TW);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+template <int TW, class T>
+__device__ __forceinline__ T team_min(T v) {
+#pragma unroll
+  for (int o = TW / 2; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, TW);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+// --------------------------------------------------------------- blocks
+// sm must hold BS/64 elements; every thread gets the result
+template <int BS, class T>
+__device__ __forceinline__ T block_sum(T v, T* sm) {
+  v = team_sum<64>(v);
+  if (lane_id() == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  T r = 0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; i++) r += sm[i];
+  __syncthreads();
+  return r;
+}
+
+template <int BS, class T>
+__device__ __forceinline__ T block_max(T v, T* sm) {
+  v = team_max<64>(v);
+  if (lane_id() == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  T r = sm[0];
+#pragma unroll
+  for (int i = 1; i < BS / 64; i++) r = sm[i] > r ? sm[i] : r;
+  __syncthreads();
+  return r;
+}
+
+template <int BS, class T>
+__device__ __forceinline__ T block_min(T v, T* sm) {
+  v = team_min<64>(v);
+  if (lane_id() == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  T r = sm[0];
+#pragma unroll
+  for (int i = 1; i < BS / 64; i++) r = sm[i] < r ? sm[i] : r;
+  __syncthreads();
+  return r;
+}
+
+// exclusive prefix over the block in thread order; *total = block sum.
+template <int BS, class T>
+__device__ __forceinline__ T block_exscan(T v, T* sm, T* total) {
+  const int l = lane_id();
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = __shfl_up(x, o, 64);
+    if (l >= o) x += y;
+  }
+  if (l == 63) sm[threadIdx.x / 64] = x;
+  __syncthreads();
+  T base = 0, tot = 0;
+  const int w = threadIdx.x / 64;
+#pragma unroll
+  for (int i = 0; i < BS / 64; i++) {
+    if (i < w) base += sm[i];
+    tot += sm[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Returns true in every thread of the block that finished last among
+// nblocks blocks sharing *ctr (which it also resets to 0).  Global writes
+// made by any block before the call are visible to the last block after it.
+__device__ __forceinline__ bool last_block(uint32_t* ctr, uint32_t nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t prev = atomicAdd(ctr, 1u);
+    s_last = (prev == nblocks - 1);
+    if (s_last) *ctr = 0;
+  }
+  __syncthreads();
+  int last = s_last;
+  if (last) __threadfence();
+  return last;
+}
+
+// Appends c to list when flag is set, one atomic per wave.  The order of
+// the list is unspecified; every consumer of it is order-independent.
+__device__ __forceinline__ void append_cand(bool flag, const Cand& c, Cand* list,
+                                            uint32_t* counter) {
+  uint64_t m = __ballot(flag);
+  if (m == 0) return;
+  int leader = __builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (flag) list[base + (uint32_t)__popcll(m & lanemask_lt())] = c;
+}
+
+// ------------------------------------------------------ admission threshold
+// Candidates are admitted in order of the key (gain desc, id asc), encoded as
+// key = ((gain - gmin) << idbits) | (2^idbits - 1 - v), larger key first.
+__device__ __forceinline__ u128 cand_key(const Cand& c, int64_t gmin, int idbits) {
+  uint64_t g = (uint64_t)(c.gain - gmin);
+  uint64_t idpart = ((1ull << idbits) - 1ull) - (uint64_t)(uint32_t)c.v;
+  return ((u128)g << idbits) | (u128)idpart;
+}
+
+struct SelShared {
+  int64_t hist[256];
+  u128 prefix;
+  int64_t above;
+  int done;
+  int pad;
+  u128 result;
+};
+
+// Radix descent over the candidate list (8-bit digits from the top).
+//   want_ge = 0: threshold of the longest prefix with weight <= bound
+//   want_ge = 1: threshold of the shortest prefix with weight >= bound (> 0)
+// Returns thr with the prefix = { key >= thr }.  Every thread of the block
+// must call it; BS is the block size.
+template <int BS>
+__device__ u128 select_prefix(const Cand* list, uint32_t ncand, int64_t gmin, int idbits,
+                              int tbits, int want_ge, int64_t bound, SelShared* sh) {
+  const int ndig = (tbits + 7) / 8;
+  if (threadIdx.x == 0) {
+    sh->prefix = 0;
+    sh->above = 0;
+    sh->done = 0;
+    sh->result = 0;
+  }
+  __syncthreads();
+  for (int d = ndig - 1; d >= 0; d--) {
+    const int shf = 8 * d;
+    for (int i = threadIdx.x; i < 256; i += BS) sh->hist[i] = 0;
+    __syncthreads();
+    const u128 P = sh->prefix;
+    for (uint32_t i = threadIdx.x; i < ncand; i += BS) {
+      Cand c = list[i];
+      u128 k = cand_key(c, gmin, idbits);
+      if ((k >> (shf + 8)) == P)
+        atomicAdd((unsigned long long*)&sh->hist[(int)((k >> shf) & 255)],
+                  (unsigned long long)c.b);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t above = sh->above;
+      int sel = -1;
+      for (int bkt = 255; bkt >= 0; bkt--) {
+        int64_t h = sh->hist[bkt];
+        if (want_ge) {
+          if (above + h >= bound) { sel = bkt; break; }
+          above += h;
+        } else {
+          if (above + h <= bound) above += h;
+          else { sel = bkt; break; }
+        }
+      }
+      sh->above = above;
+      if (sel < 0) {  // only for want_ge = 0: every candidate with this prefix fits
+        sh->result = P << (shf + 8);
+        sh->done = 1;
+      } else {
+        sh->prefix = (P << 8) | (u128)(unsigned)sel;
+      }
+    }
+    __syncthreads();
+    if (sh->done) break;
+  }
+  u128 r;
+  if (sh->done) r = sh->result;
+  else r = want_ge ? sh->prefix : sh->prefix + 1;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int bitlen64(uint64_t x) { return x == 0 ? 0 : 64 - __clzll(x); }
+
+// ------------------------------------------------------------ row sorting
+// A row of L candidates (key, val) is reduced to its distinct keys in
+// ascending order with the vals of equal keys summed (MERGE) or with a flag
+// raised on a repeated key (!MERGE).  Key INT_MAX means "drop".
+
+// one element per lane, T lanes, L <= T
+template <int T>
+__device__ __forceinline__ void team_bitonic(int32_t& k, int64_t& v) {
+  const int lane = threadIdx.x & (T - 1);
+#pragma unroll
+  for (int size = 2; size <= T; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      int32_t k2 = __shfl_xor(k, stride, T);
+      int64_t v2 = __shfl_xor(v, stride, T);
+      bool up = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      bool take = (lower == up) ? (k2 < k) : (k2 > k);
+      if (take) {
+        k = k2;
+        v = v2;
+      }
+    }
+  }
+}
+
+// after team_bitonic: writes the distinct keys, returns their count
+template <int T, bool MERGE>
+__device__ __forceinline__ int team_emit(int32_t k, int64_t v, int32_t* okey, int64_t* oval,
+                                         bool* dup) {
+  const int lane = threadIdx.x & (T - 1);
+  if (MERGE) {
+#pragma unroll
+    for (int o = 1; o < T; o <<= 1) {
+      int32_t ko = __shfl_up(k, o, T);
+      int64_t vo = __shfl_up(v, o, T);
+      if (lane >= o && ko == k) v += vo;
+    }
+  }
+  int32_t knext = __shfl_down(k, 1, T);
+  const bool valid = k != INT_MAX;
+  const bool last = (lane == T - 1) || (knext != k);
+  if (!MERGE && valid && !last) *dup = true;
+  const bool emit = valid && (MERGE ? last : true);
+  uint64_t m = __ballot(emit);
+  const int tb = lane_id() & ~(T - 1);
+  uint64_t tm = (T == 64) ? m : ((m >> tb) & ((1ull << T) - 1ull));
+  int pos = __popcll(tm & ((1ull << lane) - 1ull));
+  if (emit) {
+    okey[pos] = k;
+    oval[pos] = v;
+  }
+  return __popcll(tm);
+}
+
+__device__ __forceinline__ int next_pow2(int x) {
+  int p = 2;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// L <= kSortCap, whole block, LDS arrays sk/sv of kSortCap entries
+template <int BS, bool MERGE, class Loader>
+__device__ int block_sort_emit(int L, const Loader& ld, int32_t* sk, int64_t* sv, int32_t* okey,
+                               int64_t* oval, bool* dup, int32_t* smi) {
+  const int P2 = next_pow2(L);
+  for (int i = threadIdx.x; i < P2; i += BS) {
+    int32_t k = INT_MAX;
+    int64_t v = 0;
+    if (i < L) ld(i, k, v);
+    sk[i] = k;
+    sv[i] = v;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < P2 / 2; i += BS) {
+        int lo = (i / stride) * stride * 2 + (i % stride);
+        int hi = lo + stride;
+        bool up = (lo & size) == 0;
+        int32_t a = sk[lo], b = sk[hi];
+        if ((a > b) == up && a != b) {
+          sk[lo] = b;
+          sk[hi] = a;
+          int64_t t = sv[lo];
+          sv[lo] = sv[hi];
+          sv[hi] = t;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // distinct keys: thread t owns a chunk of consecutive slots
+  const int per = (P2 + BS - 1) / BS;
+  const int s0 = threadIdx.x * per;
+  int heads = 0;
+  for (int i = s0; i < s0 + per && i < P2; i++) {
+    if (sk[i] == INT_MAX) break;
+    if (i == 0 || sk[i - 1] != sk[i]) heads++;
+    else if (!MERGE) *dup = true;
+  }
+  int total;
+  int base = block_exscan<BS, int>(heads, smi, &total);
+  for (int i = s0; i < s0 + per && i < P2; i++) {
+    int32_t k = sk[i];
+    if (k == INT_MAX) break;
+    if (i == 0 || sk[i - 1] != k) {
+      int64_t s = sv[i];
+      if (MERGE)
+        for (int j = i + 1; j < P2 && sk[j] == k; j++) s += sv[j];
+      okey[base] = k;
+      oval[base] = s;
+      base++;
+    }
+  }
+  __syncthreads();
+  return total;
+}
+
+// any L: dense accumulation over windows of kWin ids (LDS acc/cnt/pres)
+template <int BS, bool MERGE, class Loader>
+__device__ int block_dense_emit(int L, const Loader& ld, int64_t* acc, int32_t* cnt,
+                                int32_t* smi, int64_t* sml, int32_t* okey, int64_t* oval,
+                                bool* dup) {
+  int32_t kmin = INT_MAX, kmax = -1;
+  for (int i = threadIdx.x; i < L; i += BS) {
+    int32_t k;
+    int64_t v;
+    ld(i, k, v);
+    if (k != INT_MAX) {
+      kmin = k < kmin ? k : kmin;
+      kmax = k > kmax ? k : kmax;
+    }
+  }
+  kmin = block_min<BS, int32_t>(kmin, smi);
+  kmax = block_max<BS, int32_t>(kmax, smi);
+  int out = 0;
+  if (kmax < 0) return 0;
+  for (int64_t lo = kmin; lo <= kmax; lo += kWin) {
+    for (int i = threadIdx.x; i < kWin; i += BS) {
+      acc[i] = 0;
+      cnt[i] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L; i += BS) {
+      int32_t k;
+      int64_t v;
+      ld(i, k, v);
+      if (k != INT_MAX && k >= lo && k < lo + kWin) {
+        atomicAdd((unsigned long long*)&acc[k - lo], (unsigned long long)v);
+        atomicAdd(&cnt[k - lo], 1);
+      }
+    }
+    __syncthreads();
+    constexpr int per = kWin / BS;
+    const int s0 = threadIdx.x * per;
+    int present = 0;
+    for (int j = s0; j < s0 + per; j++) {
+      present += cnt[j] > 0;
+      if (!MERGE && cnt[j] > 1) *dup = true;
+    }
+    int total;
+    int base = block_exscan<BS, int>(present, smi, &total);
+    for (int j = s0; j < s0 + per; j++)
+      if (cnt[j] > 0) {
+        okey[out + base] = (int32_t)(lo + j);
+        oval[out + base] = acc[j];
+        base++;
+      }
+    out += total;
+    __syncthreads();
+  }
+  (void)sml;
+  return out;
+}
+
+}  // namespace gpk

@@ -1,0 +1,501 @@
+// gp_driver.hip - C ABI and host driver of the single-graph path.
+//
+// The driver owns a device copy of the input graph (level 0) and the
+// buffers of every coarse level; they are kept across calls, so repeated
+// partitions of one handle allocate nothing after the first call.  Work is
+// queued on the handle's stream; the host waits only once per coarse level
+// (to learn the coarse graph's size) and once at the end.
+#include <string.h>
+
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_launch.h"
+
+using namespace gpk;
+
+namespace {
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  bool ensure(size_t n) {
+    if (n == 0) n = 1;
+    if (p && n <= cap) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc((void**)&p, n * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return false;
+    }
+    cap = n;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct Level {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  DBuf<int32_t> xadj, adj, match, cmap;
+  DBuf<int64_t> w, vc, vg;
+  DBuf<int8_t> part;
+  bool ensure(int64_t ncap, int64_t nnzcap) {
+    return xadj.ensure(ncap + 1) && adj.ensure(nnzcap) && w.ensure(nnzcap) &&
+           vc.ensure(ncap) && vg.ensure(ncap) && match.ensure(ncap) && cmap.ensure(ncap) &&
+           part.ensure(ncap);
+  }
+  void release() {
+    xadj.release(); adj.release(); match.release(); cmap.release();
+    w.release(); vc.release(); vg.release(); part.release();
+  }
+  LevelView view(int bal) const {
+    LevelView v;
+    v.n = n;
+    v.nnz = (int32_t)nnz;
+    v.xadj = xadj.p;
+    v.adj = adj.p;
+    v.w = w.p;
+    v.b = bal ? vg.p : vc.p;
+    return v;
+  }
+};
+
+uint64_t host_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+struct gp_graph {
+  hipStream_t stream = nullptr;
+  int flags = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int64_t sum[2] = {0, 0};
+  int64_t maxv[2] = {0, 0};
+  std::vector<Level*> lv;
+  // level scratch
+  DBuf<int32_t> prop, tile_lead, cmem0, cmem1, cnt, tmpk, longlist;
+  DBuf<int64_t> tile_ub, toff, tile_cnt, tmpv;
+  DBuf<Cand> list;
+  // initial bisection scratch
+  DBuf<int64_t> i_tot, i_conn, i_res;
+  DBuf<RefCtl> i_ctl;
+  DBuf<int8_t> i_part;
+  DBuf<int32_t> i_adjc;
+  DBuf<Cand> i_list;
+  Ctrl* ctrl = nullptr;
+  Ctrl* hctrl = nullptr;  // pinned
+
+  Scratch scratch() const {
+    Scratch s;
+    s.prop = prop.p;
+    s.tile_lead = tile_lead.p;
+    s.tile_ub = tile_ub.p;
+    s.cmem0 = cmem0.p;
+    s.cmem1 = cmem1.p;
+    s.toff = toff.p;
+    s.cnt = cnt.p;
+    s.tile_cnt = tile_cnt.p;
+    s.tmpk = tmpk.p;
+    s.tmpv = tmpv.p;
+    s.longlist = longlist.p;
+    s.list = list.p;
+    return s;
+  }
+  bool ensure_scratch() {
+    const int64_t n1 = n > 0 ? n : 1;
+    return prop.ensure(n1) && tile_lead.ensure(n1 / kTileV + 2) &&
+           tile_ub.ensure(n1 / kTileV + 2) && cmem0.ensure(n1) && cmem1.ensure(n1) &&
+           toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
+           tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1);
+  }
+  bool ensure_init(int32_t nl, int K) {
+    const int64_t kn = (int64_t)K * (nl > 0 ? nl : 1);
+    return i_tot.ensure(nl) && i_ctl.ensure(K) && i_part.ensure(kn) && i_conn.ensure(kn) &&
+           i_adjc.ensure(kn) && i_list.ensure(kn) && i_res.ensure(2 * (size_t)K);
+  }
+  InitScratch init_scratch() const {
+    InitScratch s;
+    s.tot = i_tot.p;
+    s.ctl = i_ctl.p;
+    s.part = i_part.p;
+    s.conn = i_conn.p;
+    s.adjc = i_adjc.p;
+    s.list = i_list.p;
+    s.res = i_res.p;
+    return s;
+  }
+  ~gp_graph() {
+    for (Level* l : lv) {
+      l->release();
+      delete l;
+    }
+    prop.release(); tile_lead.release(); cmem0.release(); cmem1.release(); cnt.release();
+    tmpk.release(); longlist.release(); tile_ub.release(); toff.release(); tile_cnt.release();
+    tmpv.release(); list.release();
+    i_tot.release(); i_conn.release(); i_res.release(); i_ctl.release(); i_part.release();
+    i_adjc.release(); i_list.release();
+    if (ctrl) (void)hipFree(ctrl);
+    if (hctrl) (void)hipHostFree(hctrl);
+  }
+};
+
+// ------------------------------------------------------------------ helpers
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) {               \
+      (void)hipGetLastError();             \
+      return GP_EDEVICE;                   \
+    }                                      \
+  } while (0)
+#define LCHK(x)                \
+  do {                         \
+    if (!(x)) return GP_EDEVICE; \
+  } while (0)
+
+static gp_status read_ctrl(gp_graph* g) {
+  HIPCHK(hipMemcpyAsync(g->hctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return GP_OK;
+}
+
+static gp_status check_options(const gp_options* o) {
+  if (!o) return GP_EINVAL;
+  const int64_t lim = (int64_t)1 << 40;
+  if (o->ratio[0] < 0 || o->ratio[1] < 0 || o->ratio[0] >= lim || o->ratio[1] >= lim ||
+      o->ratio[0] + o->ratio[1] == 0)
+    return GP_EINVAL;
+  if (o->eps_ppm < 0 || o->eps_ppm > 1000000) return GP_EINVAL;
+  if (o->balance_on != 0 && o->balance_on != 1) return GP_EINVAL;
+  if (o->coarsen_to < 1 || o->match_rounds < 0 || o->match_rounds > kMaxRounds ||
+      o->refine_passes < 0 || o->refine_passes > 64 || o->init_trials < 1 || o->init_trials > 64)
+    return GP_EINVAL;
+  if ((o->flags & GP_LEARNED) && !o->model) return GP_EMODEL;
+  return GP_OK;
+}
+
+// Eq. (1)-(2) bounds: tgt_p = floor(W r_p / R), maxw_p = ceil(W r_p (1e6+eps) / (R 1e6))
+static void host_balance(int64_t W, const int64_t* r, int32_t eps, int64_t* tgt, int64_t* maxw) {
+  const __int128 R = (__int128)r[0] + r[1];
+  for (int p = 0; p < 2; p++) {
+    tgt[p] = (int64_t)(((__int128)W * r[p]) / R);
+    const __int128 num = (__int128)W * r[p] * (1000000 + eps);
+    const __int128 den = R * 1000000;
+    maxw[p] = (int64_t)((num + den - 1) / den);
+  }
+}
+
+// ------------------------------------------------------------------- C ABI
+extern "C" {
+
+void gp_options_default(gp_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->ratio[0] = 1;
+  o->ratio[1] = 4;
+  o->eps_ppm = 30000;
+  o->balance_on = 0;
+  o->seed = 0;
+  o->coarsen_to = 2048;
+  o->match_rounds = 8;
+  o->refine_passes = 8;
+  o->init_trials = 16;
+  o->flags = 0;
+  o->model = nullptr;
+}
+
+gp_status gp_ratio_from_times(int64_t t_cpu, int64_t t_gpu, int64_t ratio[2]) {
+  if (!ratio || t_cpu < 0 || t_gpu < 0 || (t_cpu == 0 && t_gpu == 0)) return GP_EINVAL;
+  int64_t a = t_gpu, b = t_cpu;
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  ratio[0] = t_gpu / a;
+  ratio[1] = t_cpu / a;
+  return GP_OK;
+}
+
+const char* gp_strerror(gp_status s) {
+  switch (s) {
+    case GP_OK: return "ok";
+    case GP_EINVAL: return "invalid argument, option or row offsets";
+    case GP_EASYM: return "edge u-v without v-u of equal weight";
+    case GP_EDUP: return "neighbour listed twice in one row";
+    case GP_ESELF: return "self loop";
+    case GP_ERANGE: return "neighbour id out of range or negative weight";
+    case GP_EOVERFLOW: return "sum of weights reaches 2^62";
+    case GP_ENOMEM: return "out of memory";
+    case GP_EDEVICE: return "HIP runtime error";
+    case GP_EMODEL: return "learned proposal requested without a usable model";
+  }
+  return "unknown status";
+}
+
+gp_status gp_set_stream(gp_graph* g, void* stream) {
+  if (!g) return GP_EINVAL;
+  g->stream = (hipStream_t)stream;
+  return GP_OK;
+}
+
+void gp_destroy(gp_graph* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  delete g;
+}
+
+gp_status gp_create(gp_graph** out, int32_t n, const int32_t* xadj, const int32_t* adjncy,
+                    const int64_t* adjwgt, const int64_t* vwgt, int32_t flags, void* stream) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  if (n < 0) return GP_EINVAL;
+  if (n > 0 && (!xadj || !vwgt)) return GP_EINVAL;
+  gp_graph* g = new (std::nothrow) gp_graph();
+  if (!g) return GP_ENOMEM;
+  g->stream = (hipStream_t)stream;
+  g->flags = flags;
+  g->n = n;
+  const bool host = (flags & GP_HOST_PTRS) != 0;
+  const hipMemcpyKind kin = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  gp_status st = GP_OK;
+  do {
+    if (hipMalloc((void**)&g->ctrl, sizeof(Ctrl)) != hipSuccess) { st = GP_ENOMEM; break; }
+    if (hipHostMalloc((void**)&g->hctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+      g->hctrl = nullptr;
+      st = GP_ENOMEM;
+      break;
+    }
+    memset(g->hctrl, 0, sizeof(Ctrl));
+    Level* l0 = new (std::nothrow) Level();
+    if (!l0) { st = GP_ENOMEM; break; }
+    g->lv.push_back(l0);
+    if (n == 0) break;
+    int32_t nnz32 = 0;
+    if (host) {
+      nnz32 = xadj[n];
+    } else {
+      if (hipMemcpy(&nnz32, xadj + n, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+        st = GP_EDEVICE;
+        break;
+      }
+    }
+    if (nnz32 < 0) { st = GP_EINVAL; break; }
+    if (nnz32 > 0 && (!adjncy || !adjwgt)) { st = GP_EINVAL; break; }
+    g->nnz = nnz32;
+    l0->n = n;
+    l0->nnz = nnz32;
+    DBuf<int64_t> vtmp;
+    if (!l0->ensure(n, nnz32) || !vtmp.ensure(2 * (size_t)n)) { st = GP_ENOMEM; break; }
+    hipStream_t s = g->stream;
+    if (hipMemcpyAsync(l0->xadj.p, xadj, sizeof(int32_t) * (n + 1), kin, s) != hipSuccess ||
+        (nnz32 > 0 &&
+         (hipMemcpyAsync(l0->adj.p, adjncy, sizeof(int32_t) * nnz32, kin, s) != hipSuccess ||
+          hipMemcpyAsync(l0->w.p, adjwgt, sizeof(int64_t) * nnz32, kin, s) != hipSuccess)) ||
+        hipMemcpyAsync(vtmp.p, vwgt, sizeof(int64_t) * 2 * n, kin, s) != hipSuccess ||
+        hipMemsetAsync(g->ctrl, 0, sizeof(Ctrl), s) != hipSuccess) {
+      vtmp.release();
+      st = GP_EDEVICE;
+      break;
+    }
+    if (!launch_split_vwgt(n, vtmp.p, l0->vc.p, l0->vg.p, s) ||
+        !launch_validate(n, l0->xadj.p, l0->adj.p, l0->w.p, l0->vc.p, l0->vg.p, g->ctrl, 0, s)) {
+      vtmp.release();
+      st = GP_EDEVICE;
+      break;
+    }
+    st = read_ctrl(g);
+    vtmp.release();
+    if (st != GP_OK) break;
+    if (g->hctrl->verr & kVInval) { st = GP_EINVAL; break; }
+    if (!launch_validate(n, l0->xadj.p, l0->adj.p, l0->w.p, l0->vc.p, l0->vg.p, g->ctrl, 1, s)) {
+      st = GP_EDEVICE;
+      break;
+    }
+    if ((st = read_ctrl(g)) != GP_OK) break;
+    uint32_t e = g->hctrl->verr;
+    if (e & kVRange) { st = GP_ERANGE; break; }
+    if (e & kVSelf) { st = GP_ESELF; break; }
+    if (g->hctrl->vunsorted) {
+      DBuf<int32_t> na;
+      DBuf<int64_t> nw;
+      if (!na.ensure(nnz32) || !nw.ensure(nnz32)) {
+        na.release();
+        nw.release();
+        st = GP_ENOMEM;
+        break;
+      }
+      if (!launch_sort_rows(n, l0->xadj.p, l0->adj.p, l0->w.p, na.p, nw.p, g->ctrl, s) ||
+          (st = read_ctrl(g)) != GP_OK) {
+        na.release();
+        nw.release();
+        if (st == GP_OK) st = GP_EDEVICE;
+        break;
+      }
+      std::swap(l0->adj, na);
+      std::swap(l0->w, nw);
+      na.release();
+      nw.release();
+      if (g->hctrl->verr & kVDup) { st = GP_EDUP; break; }
+    }
+    if (!launch_validate(n, l0->xadj.p, l0->adj.p, l0->w.p, l0->vc.p, l0->vg.p, g->ctrl, 2, s)) {
+      st = GP_EDEVICE;
+      break;
+    }
+    if ((st = read_ctrl(g)) != GP_OK) break;
+    e = g->hctrl->verr;
+    if (e & kVAsym) { st = GP_EASYM; break; }
+    if (e & kVOverflow) { st = GP_EOVERFLOW; break; }
+    g->sum[0] = (int64_t)g->hctrl->vsum_c;
+    g->sum[1] = (int64_t)g->hctrl->vsum_g;
+    g->maxv[0] = g->hctrl->vmax_c;
+    g->maxv[1] = g->hctrl->vmax_g;
+  } while (0);
+  if (st != GP_OK) {
+    delete g;
+    return st;
+  }
+  *out = g;
+  return GP_OK;
+}
+
+static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
+                               int64_t* trace, int32_t trace_cap) {
+  if (!g || !res || (g->n > 0 && !part)) return GP_EINVAL;
+  gp_status st = check_options(o);
+  if (st != GP_OK) return st;
+  const int32_t n = g->n;
+  const int bal = o->balance_on;
+  gp_result r;
+  memset(&r, 0, sizeof(r));
+  const int64_t W = g->sum[bal];
+  int64_t tgt[2], maxw[2];
+  host_balance(W, o->ratio, o->eps_ppm, tgt, maxw);
+  if (n == 0) {
+    r.feasible = 1;
+    *res = r;
+    return GP_OK;
+  }
+  if (o->flags & GP_LEARNED) return GP_EMODEL;  // the learned proposal has its own entry
+  hipStream_t s = g->stream;
+  if (!g->ensure_scratch()) return GP_ENOMEM;
+  const int64_t C = o->coarsen_to;
+  const int R = o->match_rounds, P = o->refine_passes;
+  // control block
+  Ctrl& h = *g->hctrl;
+  memset(&h, 0, sizeof(Ctrl));
+  h.tgt[0] = tgt[0];
+  h.tgt[1] = tgt[1];
+  h.ref.maxw[0] = maxw[0];
+  h.ref.maxw[1] = maxw[1];
+  h.cap = (int64_t)(((__int128)3 * W + 2 * (__int128)C - 1) / (2 * (__int128)C));
+  h.maxb = g->maxv[bal];
+  HIPCHK(hipMemcpyAsync(g->ctrl, g->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  const Scratch sc = g->scratch();
+  std::vector<int64_t> pairs(kMaxLevels + 1, 0);
+  int L = 0;
+  while (g->lv[L]->n > C) {
+    Level* f = g->lv[L];
+    if ((int)g->lv.size() <= L + 1) {
+      Level* nl = new (std::nothrow) Level();
+      if (!nl) return GP_ENOMEM;
+      g->lv.push_back(nl);
+    }
+    Level* c = g->lv[L + 1];
+    if (!c->ensure(f->n, f->nnz)) return GP_ENOMEM;
+    const LevelView fv = f->view(bal);
+    LCHK(launch_level_reset(g->ctrl, L > 0, s));
+    const int tw = team_width_for(f->n, f->nnz);
+    const uint64_t hs = host_mix64(o->seed ^ (uint64_t)(uint32_t)L);
+    if (R == 0) HIPCHK(hipMemsetAsync(f->match.p, 0xff, sizeof(int32_t) * f->n, s));
+    for (int rr = 0; rr < R; rr++)
+      LCHK(launch_match_round(fv, f->match.p, sc.prop, g->ctrl, rr, hs, tw, s));
+    LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
+    LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
+                           c->vg.p, s));
+    LCHK(launch_contract_b(fv, f->cmap.p, g->ctrl, sc, f->n, c->xadj.p, c->adj.p, c->w.p, s));
+    if ((st = read_ctrl(g)) != GP_OK) return st;
+    c->n = h.nc;
+    c->nnz = h.nnz_c;
+    pairs[L] = (int64_t)f->n - c->n;
+    L++;
+    if (20 * (int64_t)c->n > 19 * (int64_t)f->n || L == kMaxLevels) break;
+  }
+  // coarsest level: greedy-growing trials
+  {
+    Level* cl = g->lv[L];
+    const int K = o->init_trials < cl->n ? o->init_trials : cl->n;
+    if (!g->ensure_init(cl->n, K)) return GP_ENOMEM;
+    const int gs = o->ratio[0] <= o->ratio[1] ? 0 : 1;
+    LCHK(launch_init(cl->view(bal), K, gs, P, g->ctrl, g->init_scratch(), cl->part.p, s));
+  }
+  auto record = [&](int l, bool coarsest) -> gp_status {
+    if (!trace || l >= trace_cap) return GP_OK;
+    Level* lvl = g->lv[l];
+    LCHK(launch_final_stats(lvl->view(bal), lvl->vc.p, lvl->vg.p, lvl->part.p, g->ctrl,
+                            team_width_for(lvl->n, lvl->nnz), s));
+    gp_status e2 = read_ctrl(g);
+    if (e2 != GP_OK) return e2;
+    int64_t* t = trace + 8 * l;
+    t[0] = lvl->n;
+    t[1] = lvl->nnz;
+    t[2] = coarsest ? 0 : h.ref.pass;
+    t[3] = coarsest ? 0 : h.ref.total_moves;
+    t[4] = h.res_ext / 2;
+    t[5] = h.res_load[0];
+    t[6] = h.res_load[1];
+    t[7] = pairs[l];
+    return GP_OK;
+  };
+  if ((st = record(L, true)) != GP_OK) return st;
+  for (int l = L - 1; l >= 0; l--) {
+    Level* f = g->lv[l];
+    Level* c = g->lv[l + 1];
+    LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, s));
+    const int tw = team_width_for(f->n, f->nnz);
+    const LevelView fv = f->view(bal);
+    for (int p = 0; p < P; p++) LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, tw, s));
+    if ((st = record(l, false)) != GP_OK) return st;
+  }
+  Level* l0 = g->lv[0];
+  LCHK(launch_final_stats(l0->view(bal), l0->vc.p, l0->vg.p, l0->part.p, g->ctrl,
+                          team_width_for(l0->n, l0->nnz), s));
+  const hipMemcpyKind kout =
+      (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HIPCHK(hipMemcpyAsync(part, l0->part.p, (size_t)n, kout, s));
+  if ((st = read_ctrl(g)) != GP_OK) return st;
+  r.cut = h.res_ext / 2;
+  r.load[0] = h.res_load[0];
+  r.load[1] = h.res_load[1];
+  r.time[0] = h.res_time[0];
+  r.time[1] = h.res_time[1];
+  r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
+  r.levels = L;
+  r.used_learned = 0;
+  *res = r;
+  return GP_OK;
+}
+
+gp_status gp_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res) {
+  return run_partition(g, o, part, res, nullptr, 0);
+}
+
+gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
+                             int64_t* trace, int32_t trace_cap) {
+  return run_partition(g, o, part, res, trace, trace_cap);
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// gp_internal.h - layouts shared by the host driver and the gfx950 kernels.
+//
+// Vertex ids are int32, weights, gains, cut and loads int64.  A level of the
+// multilevel hierarchy is a symmetric CSR graph with rows sorted by
+// neighbour id and two cost columns (cpu, gpu) kept as separate arrays, so
+// the balance column is one contiguous int64 stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpk {
+
+constexpr int kBlock = 256;       // threads per block of the level kernels
+constexpr int kTileV = 1024;      // vertices per tile of the ordered-scan kernels
+constexpr int kTileC = 256;       // coarse rows per tile of the row-sort kernel
+constexpr int kSortCap = 4096;    // longest candidate row sorted in LDS by one block
+constexpr int kWin = 4096;        // id window of the dense long-row merge
+constexpr int kMaxLevels = 48;
+constexpr int kMaxRounds = 64;
+constexpr int kInitBlock = 64;    // one wave per greedy-growing trial
+
+// candidate of a refinement pass: admission order is gain desc, id asc
+struct Cand {
+  int64_t gain;
+  int64_t b;
+  int32_t v;
+  int32_t pad;
+};
+
+enum : int32_t { kAdmitNone = 0, kAdmitAll = 1, kAdmitThr = 2 };
+
+// one refinement state (the whole-graph one, or one per initial trial)
+struct RefCtl {
+  int64_t pw[2];
+  int64_t maxw[2];
+  int32_t pass, z, done, npass;   // npass = P
+  int32_t mode, s;                // mode 0 improvement, 1 rebalance; s = side that moves
+  int32_t admit, idbits;
+  uint64_t thr_hi, thr_lo;        // admit iff key >= thr (128-bit key)
+  int64_t gmin;                   // gain offset of the key
+  // per-pass accumulators, cleared after each pass
+  int64_t ext_sum;                // sum over vertices of ext = 2 x cut at pass start
+  int64_t cand_b;
+  int64_t gmin_acc, gmax_acc;
+  uint32_t ncand;
+  uint32_t pad0;
+  int64_t moved_b, moved_n;
+  // totals
+  int64_t total_moves;
+  int64_t last_cut;
+  uint32_t ctr_gain, ctr_apply;   // last-block counters
+};
+
+struct Ctrl {
+  RefCtl ref;
+  int64_t tgt[2];
+  int64_t cap;            // matching weight cap
+  int64_t maxb;           // largest balance weight on the current level
+  int32_t made[kMaxRounds];
+  // contraction
+  int32_t nc, nnz_c, nlong, pad1;
+  int64_t ubtot;
+  int64_t maxb_next;
+  uint32_t ctr_count, ctr_long, ctr_stats, ctr_init;
+  int32_t niso;           // unmatched vertices without neighbours
+  uint32_t ctr_iso;
+  // result of the final statistics kernel
+  int64_t res_ext, res_load[2], res_time[2];
+  // validation
+  uint32_t verr;          // bit flags
+  uint32_t vunsorted;
+  uint64_t vsum_w, vsum_c, vsum_g;
+  int64_t vmax_c, vmax_g;
+};
+
+// validation flag bits
+enum : uint32_t {
+  kVInval = 1u, kVRange = 2u, kVSelf = 4u, kVDup = 8u, kVAsym = 16u, kVOverflow = 32u
+};
+
+// device view of one level
+struct LevelView {
+  int32_t n, nnz;
+  const int32_t* xadj;
+  const int32_t* adj;
+  const int64_t* w;
+  const int64_t* b;     // balance column
+};
+
+}  // namespace gpk

@@ -1,0 +1,217 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Every case prints its name before touching the GPU.  Sizes span one to many
+tiles with ragged tails; the full-size 4M-vertex layered DAG is checked
+against the oracle's stored digest (tests/golden/, written by
+make_golden.py from the oracle only).
+"""
+import hashlib
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import dagen
+import oracle
+from helpers import complete_graph, edgeless_graph, path_graph, random_graph
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def opts_pair(gp, **kw):
+    return gp.options(**kw), oracle.Options(**{k: v for k, v in kw.items()})
+
+
+def run_both(gp, g, trace=True, **kw):
+    go, oo = opts_pair(gp, **kw)
+    say(f"case {g.name} n={g.n} nnz={g.nnz} opts={kw}")
+    ref = oracle.partition(g, oo)
+    assert ref.status == 0
+    h = gp.create(g)
+    if trace:
+        part, res, tr = h.partition(go, trace_cap=64)
+    else:
+        part, res = h.partition(go)
+        tr = None
+    got = part.cpu().numpy()
+    h.close()
+    return ref, got, res, tr
+
+
+def assert_same(ref, got, res, tr=None):
+    if tr is not None and len(ref.trace):
+        n = min(len(tr), len(ref.trace))
+        for l in range(n - 1, -1, -1):
+            assert np.array_equal(tr[l], ref.trace[l]), (
+                f"level {l}: gpu {tr[l].tolist()} vs oracle {ref.trace[l].tolist()}")
+        assert len(tr) == len(ref.trace)
+    assert res.levels == ref.levels
+    assert np.array_equal(got, ref.part), f"{int((got != ref.part).sum())} vertices differ"
+    assert res.cut == ref.cut
+    assert (res.load[0], res.load[1]) == ref.load
+    assert (res.time[0], res.time[1]) == ref.time
+    assert res.feasible == ref.feasible
+
+
+def test_cholesky8(gp):
+    g = dagen.config_cholesky8()
+    assert_same(*run_both(gp, g))
+
+
+@pytest.mark.parametrize("which", [0, 1], ids=["cholesky64", "lu48"])
+def test_cholesky64_lu48(gp, which):
+    g = dagen.config_cholesky64_lu48()[which]
+    assert_same(*run_both(gp, g))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_with_coarsening(gp, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 400))
+    g = random_graph(n, float(rng.uniform(0.005, 0.2)), rng, wmax=int(rng.choice([1, 9, 1000])),
+                     vmax=int(rng.choice([1, 9, 100])), const_w=bool(seed % 3 == 0),
+                     name=f"rand{seed}")
+    kw = dict(ratio=[(1, 4), (1, 1), (3, 1), (2, 7)][seed % 4],
+              eps_ppm=int(rng.choice([0, 30000, 200000])), balance_on=seed % 2, seed=seed,
+              coarsen_to=int(rng.choice([2, 8, 32, 2048])),
+              match_rounds=int(rng.choice([0, 1, 8])), refine_passes=int(rng.choice([0, 1, 8])),
+              init_trials=int(rng.choice([1, 5, 16])))
+    assert_same(*run_both(gp, g, **kw))
+
+
+@pytest.mark.parametrize("n,L,seed", [(5000, 8, 1), (77777, 16, 2), (262147, 64, 3)])
+def test_layered_parity(gp, n, L, seed):
+    g = dagen.layered(n, L, rate=3, seed=seed)
+    assert_same(*run_both(gp, g, ratio=(1, 3), eps_ppm=50000))
+
+
+@pytest.mark.parametrize("T", [12, 30])
+def test_jittered_cholesky_lu(gp, T):
+    for g in (dagen.cholesky(T, 256, jitter_pm=100, seed=T), dagen.lu(T, 256, jitter_pm=100,
+                                                                          seed=T)):
+        assert_same(*run_both(gp, g, coarsen_to=64))
+        assert_same(*run_both(gp, g, balance_on=1, ratio=(2, 5), coarsen_to=256))
+
+
+def test_special_graphs(gp):
+    for g, kw in ((path_graph(3000), dict()), (complete_graph(200), dict(coarsen_to=16)),
+                  (edgeless_graph(5000, np.arange(5000) % 17 + 1), dict(coarsen_to=64)),
+                  (dagen.config_cholesky8(), dict(ratio=(0, 1))),
+                  (dagen.config_cholesky8(), dict(ratio=(1, 0))),
+                  (path_graph(1), dict()), (path_graph(2), dict())):
+        g.name = g.name or "special"
+        assert_same(*run_both(gp, g, **kw))
+
+
+def test_unsorted_rows_canonicalised(gp):
+    rng = np.random.default_rng(5)
+    g = dagen.layered(20000, 16, rate=3, seed=9)
+    ref = oracle.partition(g)
+    adj, w = g.adjncy.copy(), g.adjwgt.copy()
+    for u in range(g.n):
+        s, e = g.xadj[u], g.xadj[u + 1]
+        p = rng.permutation(e - s)
+        adj[s:e], w[s:e] = adj[s:e][p], w[s:e][p]
+    g2 = dagen.Graph(g.n, g.xadj, adj, w, g.vwgt, "shuffled")
+    say("case shuffled rows")
+    h = gp.create(g2)
+    part, res = h.partition(gp.options())
+    assert np.array_equal(part.cpu().numpy(), ref.part) and res.cut == ref.cut
+    h.close()
+
+
+def test_long_rows_and_hubs(gp):
+    # a hub joined to every vertex (a long row at every level) plus a sparse rest
+    n = 20000
+    rng = np.random.default_rng(3)
+    src = np.concatenate([np.zeros(n - 1, np.int32), rng.integers(1, n, 30000).astype(np.int32)])
+    dst = np.concatenate([np.arange(1, n, dtype=np.int32), rng.integers(1, n, 30000).astype(
+        np.int32)])
+    keep = src != dst
+    g = dagen.to_csr(n, src[keep], dst[keep], rng.integers(1, 50, keep.sum()).astype(np.int64),
+                     rng.integers(1, 9, (n, 2)).astype(np.int64), "hub20k")
+    assert_same(*run_both(gp, g, coarsen_to=100))
+
+
+def test_determinism_repeat(gp):
+    g = dagen.layered(100000, 32, rate=3, seed=4)
+    h = gp.create(g)
+    outs = []
+    for i in range(3):
+        say(f"case repeat {i}")
+        part, res = h.partition(gp.options(ratio=(1, 3)))
+        outs.append((part.cpu().numpy().copy(), res.cut, res.load[0]))
+    h.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1:] == outs[0][1:]
+
+
+def _bad_cases():
+    g = path_graph(5)
+    base = dict(xadj=g.xadj, adj=g.adjncy, w=g.adjwgt, vw=g.vwgt)
+    out = []
+
+    def mk(name, code, **mods):
+        c = {k: v.copy() for k, v in base.items()}
+        for k, f in mods.items():
+            f(c[k])
+        out.append((name, c, code))
+
+    mk("xadj0", oracle.EINVAL, xadj=lambda a: a.__setitem__(0, 1))
+    mk("range", oracle.ERANGE, adj=lambda a: a.__setitem__(0, 7))
+    mk("negw", oracle.ERANGE, w=lambda a: a.__setitem__(3, -1))
+    mk("negv", oracle.ERANGE, vw=lambda a: a.__setitem__((2, 1), -5))
+    mk("self", oracle.ESELF, adj=lambda a: a.__setitem__(1, 1))
+    mk("dup", oracle.EDUP, adj=lambda a: a.__setitem__(2, 0))
+    mk("asym_w", oracle.EASYM, w=lambda a: a.__setitem__(0, 2))
+    mk("asym_e", oracle.EASYM, adj=lambda a: a.__setitem__(2, 3))
+    mk("overflow", oracle.EOVERFLOW, w=lambda a: a.__setitem__(slice(None), 1 << 60))
+    return out
+
+
+@pytest.mark.parametrize("name,c,code", _bad_cases(), ids=[x[0] for x in _bad_cases()])
+def test_create_errors_match_oracle(gp, name, c, code):
+    import torch
+    say(f"case error {name}")
+    r = oracle.partition(n=5, xadj=c["xadj"], adjncy=c["adj"], adjwgt=c["w"], vwgt=c["vw"])
+    assert r.status == code
+    dev = [torch.from_numpy(np.ascontiguousarray(c[k])).cuda() for k in ("xadj", "adj", "w")]
+    vw = torch.from_numpy(np.ascontiguousarray(c["vw"]).reshape(-1)).cuda()
+    assert gp.create_status(5, *dev, vw, host=False) == code
+    assert gp.create_status(5, c["xadj"], c["adj"], c["w"], np.ascontiguousarray(c["vw"]),
+                            host=True) == code
+
+
+def test_host_pointer_path(gp):
+    g = dagen.layered(30000, 16, rate=3, seed=8)
+    ref = oracle.partition(g)
+    say("case host pointers")
+    h = gp.Graph(g.n, g.xadj, g.adjncy, g.adjwgt, np.ascontiguousarray(g.vwgt))
+    part, res = h.partition(gp.options())
+    h.close()
+    assert np.array_equal(part, ref.part) and res.cut == ref.cut
+
+
+def test_layered4m_full_size(gp):
+    """The 4,000,000-vertex layered DAG at its full size, in the launch
+    configuration the benchmark times, against the oracle's stored digest."""
+    path = os.path.join(HERE, "golden", "layered4m_1to3_eps5.txt")
+    exp = dict(l.split("=", 1) for l in open(path).read().split("\n") if "=" in l)
+    g = dagen.config_layered4m()
+    say("case layered4m full size")
+    h = gp.create(g)
+    part, res = h.partition(gp.options(ratio=(1, 3), eps_ppm=50000))
+    got = part.cpu().numpy()
+    h.close()
+    assert hashlib.sha256(got.tobytes()).hexdigest() == exp["part_sha256"]
+    assert res.cut == int(exp["cut"]) and res.levels == int(exp["levels"])
+    assert (res.load[0], res.load[1]) == (int(exp["load0"]), int(exp["load1"]))
+    assert (res.time[0], res.time[1]) == (int(exp["time0"]), int(exp["time1"]))
