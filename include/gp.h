@@ -82,7 +82,7 @@ typedef struct {
   int32_t feasible;      /* load[p] <= maxw[p] for both parts */
   int32_t levels;        /* number of coarse graphs built */
   int32_t used_learned;  /* 1 when the learned proposal beat the plain one */
-  int32_t reserved;
+  int32_t status;        /* gp_status of this graph (batched calls); GP_OK otherwise */
 } gp_result;
 
 /* Fill *o with the defaults: ratio 1:4, eps 3 %, CPU column, seed 0, 2048, 8, 8, 16. */
@@ -119,6 +119,51 @@ gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_
                              int64_t* trace, int32_t trace_cap);
 
 void gp_destroy(gp_graph* g);
+
+/* Per-kernel profile of the calls made while profiling is on (HIP events
+ * around every launch; adds a host wait per level).  One row per kernel (and
+ * team width): */
+typedef struct {
+  char name[40];        /* kernel, e.g. "k_refine_gain<8>" */
+  int64_t launches;     /* launches recorded */
+  int64_t executed;     /* launches that did their work; the others exited on a device flag */
+  double ms;            /* summed event time of all launches, milliseconds */
+  double bytes;         /* algorithmic bytes moved by the executed launches (0: not defined) */
+} gp_prof_row;
+
+/* on != 0 starts recording on this handle; on == 0 stops. */
+gp_status gp_profile_enable(gp_graph* g, int32_t on);
+/* Copies at most cap rows (host memory) and returns the row count (or -1);
+ * reset != 0 clears the accumulated rows afterwards. */
+int32_t gp_profile_read(gp_graph* g, gp_prof_row* rows, int32_t cap, int32_t reset);
+
+/* ---------------------------------------------------------------------
+ * Batched partition: many independent graphs in one persistent kernel
+ * (one workgroup per graph, largest graphs first), launched as a captured
+ * hipGraph.  Each graph's result equals gp_create + gp_partition on that
+ * graph alone with the same options.
+ *
+ * Layout (device memory): graph g owns vertices voff[g]..voff[g+1] and CSR
+ * entries eoff[g]..eoff[g+1] (int64[G+1] each, voff[0] = eoff[0] = 0); its
+ * xadj has n_g+1 local offsets starting at 0 and sits at
+ * xadj[voff[g]+g .. voff[g+1]+g]; adjncy holds local vertex ids; vwgt is
+ * int64[voff[G]][2]; part receives int8[voff[G]].  res: host array of G
+ * results, res[g].status holds that graph's check result (GP_ERANGE, ...).
+ * GP_LEARNED is not available here (GP_EMODEL).
+ * --------------------------------------------------------------------- */
+typedef struct gp_batch gp_batch;
+
+/* A batch context owning the device scratch (reused by later calls). */
+gp_status gp_batch_create(gp_batch** b, void* stream);
+/* workgroups: persistent workgroups (0 = two per compute unit); chunk:
+ * graphs taken per queue pop; order_mode: 0 largest first, 1 input order.
+ * None of them changes any result. */
+gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode);
+gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
+                             const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
+                             const int64_t* vwgt, const gp_options* o, int8_t* part,
+                             gp_result* res);
+void gp_batch_destroy(gp_batch* b);
 
 const char* gp_strerror(gp_status s);
 

@@ -56,6 +56,14 @@ def _load():
     lib.or_init_bisect.argtypes = [i32, vp, vp, vp, vp, i64, i64, vp, vp, ctypes.c_int,
                                    ctypes.c_int, vp, vp]
     lib.or_partition.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
+    lib.or_mpnn_nparam.restype = i32
+    lib.or_phi.restype = ctypes.c_float
+    lib.or_phi.argtypes = [i64]
+    lib.or_mpnn_scores.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_bf16_round.restype = ctypes.c_uint16
+    lib.or_bf16_round.argtypes = [ctypes.c_float]
+    lib.or_mpnn_loss_grad_f64.restype = ctypes.c_double
+    lib.or_mpnn_loss_grad_f64.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -221,3 +229,42 @@ def partition(graph=None, opts: Options | None = None, *, n=None, xadj=None, adj
     tr = trace.reshape(trace_cap, 8)[:levels + 1].copy() if rc == OK and n > 0 else trace[:0]
     return Result(rc, part[:n].copy(), int(res[0]), (int(res[1]), int(res[2])),
                   (int(res[3]), int(res[4])), int(res[5]), levels, int(res[7]), tr)
+
+
+# ------------------------------------------------------------ learned part
+def mpnn_nparam() -> int:
+    return int(_load().or_mpnn_nparam())
+
+
+def phi(x: int) -> float:
+    return float(_load().or_phi(int(x)))
+
+
+def mpnn_scores(g, params_bf16: np.ndarray) -> np.ndarray:
+    """Exact FP32/BF16 emulation of the network's inference (float32[n])."""
+    P = _c(params_bf16, np.uint16)
+    assert P.size == mpnn_nparam()
+    out = np.zeros(max(g.n, 1), np.float32)
+    vc = _c(g.vwgt[:, 0], np.int64)
+    vg = _c(g.vwgt[:, 1], np.int64)
+    rc = _load().or_mpnn_scores(g.n, _p(_c(g.xadj, np.int32)), _p(_c(g.adjncy, np.int32)),
+                                _p(_c(g.adjwgt, np.int64)), _p(vc), _p(vg), _p(P), _p(out))
+    assert rc == 0
+    return out[:g.n]
+
+
+def mpnn_loss_grad_f64(g, bw: np.ndarray, labels: np.ndarray, params: np.ndarray):
+    """FP64 training objective and gradient (no rounding anywhere)."""
+    P = _c(params, np.float64)
+    grad = np.zeros(mpnn_nparam(), np.float64)
+    vc = _c(g.vwgt[:, 0], np.int64)
+    vg = _c(g.vwgt[:, 1], np.int64)
+    loss = _load().or_mpnn_loss_grad_f64(g.n, _p(_c(g.xadj, np.int32)), _p(_c(g.adjncy, np.int32)),
+                                         _p(_c(g.adjwgt, np.int64)), _p(vc), _p(vg),
+                                         _p(_c(bw, np.int64)), _p(_c(labels, np.int8)), _p(P),
+                                         _p(grad))
+    return float(loss), grad
+
+
+def bf16_round(f: float) -> int:
+    return int(_load().or_bf16_round(float(f)))

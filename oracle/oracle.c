@@ -36,14 +36,7 @@ enum { OR_OK = 0, OR_EINVAL = 1, OR_EASYM = 2, OR_EDUP = 3, OR_ESELF = 4, OR_ERA
 #define OR_LIM62 ((int64_t)1 << 62)
 #define OR_RATIO_LIM ((int64_t)1 << 40)
 
-typedef struct {
-  int32_t n;
-  int32_t* xadj;
-  int32_t* adj;
-  int64_t* w;
-  int64_t* vc; /* cost on the CPU */
-  int64_t* vg; /* cost on the GPU */
-} OG;
+#include "oracle_internal.h"
 
 static void og_free(OG* g) {
   free(g->xadj); free(g->adj); free(g->w); free(g->vc); free(g->vg);
@@ -624,8 +617,6 @@ int or_init_bisect(int32_t n, const int32_t* xadj, const int32_t* adj, const int
 /* ------------------------------------------------------------------------ */
 /* Learned proposal hook: defined in mpnn.c.                                 */
 /* ------------------------------------------------------------------------ */
-int or_learned_proposal(const OG* g, const int64_t* b, const void* model, int gs,
-                        const int64_t* tgt, const int64_t* maxw, int8_t* part, int64_t* pw);
 
 /* ------------------------------------------------------------------------ */
 /* Whole multilevel partition.                                               */

@@ -44,12 +44,17 @@ class Result(ctypes.Structure):
     _fields_ = [("cut", ctypes.c_int64), ("load", ctypes.c_int64 * 2),
                 ("time", ctypes.c_int64 * 2), ("feasible", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("used_learned", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return dict(cut=self.cut, load=(self.load[0], self.load[1]),
                     time=(self.time[0], self.time[1]), feasible=self.feasible,
-                    levels=self.levels, used_learned=self.used_learned)
+                    levels=self.levels, used_learned=self.used_learned, status=self.status)
+
+
+class ProfRow(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("executed", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 def _load():
@@ -72,6 +77,19 @@ def _load():
     lib.gp_partition_trace.restype = ctypes.c_int
     lib.gp_destroy.argtypes = [vp]
     lib.gp_destroy.restype = None
+    lib.gp_profile_enable.argtypes = [vp, i32]
+    lib.gp_profile_enable.restype = ctypes.c_int
+    lib.gp_profile_read.argtypes = [vp, ctypes.POINTER(ProfRow), i32, i32]
+    lib.gp_profile_read.restype = i32
+    lib.gp_batch_create.argtypes = [ctypes.POINTER(vp), vp]
+    lib.gp_batch_create.restype = ctypes.c_int
+    lib.gp_batch_config.argtypes = [vp, i32, i32, i32]
+    lib.gp_batch_config.restype = ctypes.c_int
+    lib.gp_partition_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options),
+                                       vp, ctypes.POINTER(Result)]
+    lib.gp_partition_batch.restype = ctypes.c_int
+    lib.gp_batch_destroy.argtypes = [vp]
+    lib.gp_batch_destroy.restype = None
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_strerror.restype = ctypes.c_char_p
     return lib
@@ -80,7 +98,9 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["gp_options_default", "gp_ratio_from_times", "gp_create", "gp_set_stream",
-            "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror"]
+            "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror",
+            "gp_profile_enable", "gp_profile_read", "gp_batch_create", "gp_batch_config",
+            "gp_partition_batch", "gp_batch_destroy"]
 
 
 def strerror(status: int) -> str:
@@ -175,6 +195,18 @@ class Graph:
             return part, res, tr.reshape(trace_cap, 8)[:res.levels + 1].copy()
         return part, res
 
+    def profile(self, on: bool = True):
+        """Start (or stop) per-launch event timing on this handle."""
+        _lib.gp_profile_enable(self._h, 1 if on else 0)
+
+    def profile_read(self, reset: bool = True) -> list:
+        """Per-kernel rows: name, launches, executed, ms, bytes."""
+        n = _lib.gp_profile_read(self._h, None, 0, 0)
+        rows = (ProfRow * max(n, 1))()
+        n = _lib.gp_profile_read(self._h, rows, n, 1 if reset else 0)
+        return [dict(name=r.name.decode(), launches=r.launches, executed=r.executed, ms=r.ms,
+                     bytes=r.bytes) for r in rows[:n]]
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.gp_destroy(self._h)
@@ -211,3 +243,56 @@ def to_device(g, device="cuda"):
 def create(g, device="cuda", stream=None) -> Graph:
     """gp_create from an object with n, xadj, adjncy, adjwgt, vwgt (numpy) on a device."""
     return Graph(*to_device(g, device), stream=stream)
+
+
+class Batch:
+    """A batch context (gp_batch_create) for partitioning many graphs per call."""
+
+    def __init__(self, stream=None):
+        self.stream = stream if stream is not None else _current_stream()
+        h = ctypes.c_void_p()
+        st = _lib.gp_batch_create(ctypes.byref(h), self.stream)
+        if st != OK:
+            raise GPError(st, "gp_batch_create")
+        self._h = h
+
+    def config(self, workgroups: int = 0, chunk: int = 1, order_mode: int = 0):
+        st = _lib.gp_batch_config(self._h, workgroups, chunk, order_mode)
+        if st != OK:
+            raise GPError(st, "gp_batch_config")
+
+    def partition(self, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, opts=None, part=None):
+        """Device tensors in the concatenated layout of include/gp.h.
+        Returns (part, list of Result)."""
+        import torch
+        opts = opts or options()
+        if part is None:
+            part = torch.empty(max(int(vwgt.numel()) // 2, 1), dtype=torch.int8,
+                               device=xadj.device)
+        res = (Result * max(G, 1))()
+        st = _lib.gp_partition_batch(self._h, int(G), _ptr(voff), _ptr(eoff), _ptr(xadj),
+                                     _ptr(adjncy), _ptr(adjwgt), _ptr(vwgt), ctypes.byref(opts),
+                                     _ptr(part), res)
+        if st != OK:
+            raise GPError(st, "gp_partition_batch")
+        return part, list(res[:G])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_to_device(b, device="cuda"):
+    """Device tensors (G, voff, eoff, xadj, adjncy, adjwgt, vwgt) of a concatenated batch."""
+    import torch
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    return (b.G, t(b.voff, np.int64), t(b.eoff, np.int64), t(b.xadj, np.int32),
+            t(b.adjncy, np.int32), t(b.adjwgt, np.int64),
+            t(np.ascontiguousarray(b.vwgt).reshape(-1), np.int64))

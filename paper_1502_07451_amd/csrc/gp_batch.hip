@@ -1,0 +1,758 @@
+// gp_batch.hip - batched partition: thousands of independent DAGs in one
+// persistent kernel, one workgroup per graph, captured in a hipGraph.
+//
+// Each workgroup pops graphs from an atomic queue (largest first) and runs
+// the whole pipeline of gp_create + gp_partition for it with the phase
+// bodies of gp_phases.h called at workgroup scope (bid 0 of 1 block).  The
+// coarse levels of a graph are bump-allocated from a device arena; a graph
+// that does not fit reports GP_ENOMEM and the host reruns it with a larger
+// arena.  Results are independent of the queue order, of the number of
+// workgroups and of the arena layout: each graph's computation reads and
+// writes only its own data, with integer arithmetic.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_launch.h"
+#include "gp_phases.h"
+
+namespace gpk {
+
+constexpr int kBatchLevels = kMaxLevels + 1;
+
+struct LevelRec {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* xadj;
+  const int32_t* adj;
+  const int64_t* w;
+  int64_t* vc;
+  int64_t* vg;
+  int32_t* match;
+  int32_t* cmap;
+  int8_t* part;
+};
+
+struct BatchArgs {
+  int32_t G;
+  const int64_t* voff;
+  const int64_t* eoff;
+  const int32_t* xadj;
+  const int32_t* adj;
+  const int64_t* w;
+  const int64_t* vwgt;
+  const int32_t* order;
+  int8_t* part;
+  gp_result* res;
+  int64_t r0, r1;
+  int32_t eps, bal;
+  uint64_t seed;
+  int32_t C, R, P, K;
+  uint32_t* head;
+  unsigned char* arena;
+  uint64_t arena_cap;
+  unsigned long long* arena_off;
+  unsigned char* wgs;
+  uint64_t wgs_stride;
+  int32_t nmax;
+  int32_t nnzmax;
+  int32_t chunk;
+};
+
+// per-workgroup scratch carved from wgs + blockIdx.x * wgs_stride
+struct WgScratch {
+  Ctrl* ctrl;
+  LevelRec* lev;
+  Scratch sc;
+  int64_t* tot;
+  RefCtl* tctl;
+  int8_t* tpart;
+  int64_t* tres;
+  int32_t* pass_sink;
+};
+
+__host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+// offsets of the per-workgroup scratch; returns its size
+__host__ __device__ inline uint64_t wg_layout(int32_t nmax, int32_t nnzmax, uint64_t* off) {
+  const uint64_t n1 = (uint64_t)(nmax > 0 ? nmax : 1), m1 = (uint64_t)(nnzmax > 0 ? nnzmax : 1);
+  const uint64_t sizes[] = {
+      sizeof(Ctrl), sizeof(LevelRec) * kBatchLevels,
+      4 * n1,                      // prop
+      4 * (n1 / kTileV + 2),       // tile_lead
+      8 * (n1 / kTileV + 2),       // tile_ub
+      4 * n1, 4 * n1,              // cmem0, cmem1
+      8 * n1,                      // toff
+      4 * n1,                      // cnt
+      8 * (n1 / kTileC + 2),       // tile_cnt
+      4 * m1, 8 * m1,              // tmpk, tmpv
+      4 * n1,                      // longlist
+      sizeof(Cand) * n1,           // list
+      8 * n1,                      // tot
+      sizeof(RefCtl) * 64,         // tctl
+      64 * (uint64_t)kTrialLdsMax, // tpart
+      8 * 128,                     // tres
+      64};                         // pass sink
+  uint64_t o = 0;
+  for (int i = 0; i < (int)(sizeof(sizes) / sizeof(sizes[0])); i++) {
+    off[i] = o;
+    o = align256(o + sizes[i]);
+  }
+  return o;
+}
+
+__device__ WgScratch wg_scratch(const BatchArgs& a) {
+  uint64_t off[32];
+  wg_layout(a.nmax, a.nnzmax, off);
+  unsigned char* base = a.wgs + (uint64_t)blockIdx.x * a.wgs_stride;
+  WgScratch s;
+  s.ctrl = (Ctrl*)(base + off[0]);
+  s.lev = (LevelRec*)(base + off[1]);
+  s.sc.prop = (int32_t*)(base + off[2]);
+  s.sc.tile_lead = (int32_t*)(base + off[3]);
+  s.sc.tile_ub = (int64_t*)(base + off[4]);
+  s.sc.cmem0 = (int32_t*)(base + off[5]);
+  s.sc.cmem1 = (int32_t*)(base + off[6]);
+  s.sc.toff = (int64_t*)(base + off[7]);
+  s.sc.cnt = (int32_t*)(base + off[8]);
+  s.sc.tile_cnt = (int64_t*)(base + off[9]);
+  s.sc.tmpk = (int32_t*)(base + off[10]);
+  s.sc.tmpv = (int64_t*)(base + off[11]);
+  s.sc.longlist = (int32_t*)(base + off[12]);
+  s.sc.list = (Cand*)(base + off[13]);
+  s.tot = (int64_t*)(base + off[14]);
+  s.tctl = (RefCtl*)(base + off[15]);
+  s.tpart = (int8_t*)(base + off[16]);
+  s.tres = (int64_t*)(base + off[17]);
+  s.pass_sink = (int32_t*)(base + off[18]);
+  return s;
+}
+
+// bump allocation from the arena by thread 0, broadcast to the block;
+// nullptr when the arena is exhausted
+__device__ void* arena_alloc(const BatchArgs& a, uint64_t bytes) {
+  __shared__ void* s_ptr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t b = align256(bytes > 0 ? bytes : 1);
+    const uint64_t off = atomicAdd(a.arena_off, (unsigned long long)b);
+    s_ptr = (off + b <= a.arena_cap) ? (void*)(a.arena + off) : nullptr;
+  }
+  __syncthreads();
+  return s_ptr;
+}
+
+__device__ int team_width_dev(int32_t n, int32_t nnz) {
+  // same thresholds as the single-graph path (avg degree 6, 12, 24, 48)
+  if (n <= 0) return 4;
+  const int64_t m = nnz;
+  if (m <= 6ll * n) return 4;
+  if (m <= 12ll * n) return 8;
+  if (m <= 24ll * n) return 16;
+  if (m <= 48ll * n) return 32;
+  return 64;
+}
+
+#define TW_DISPATCH(tw, CALL)        \
+  switch (tw) {                      \
+    case 4: { constexpr int TWv = 4; CALL; } break;   \
+    case 8: { constexpr int TWv = 8; CALL; } break;   \
+    case 16: { constexpr int TWv = 16; CALL; } break; \
+    case 32: { constexpr int TWv = 32; CALL; } break; \
+    default: { constexpr int TWv = 64; CALL; } break; \
+  }
+
+__device__ void write_status(const BatchArgs& a, int g, int32_t st) {
+  if (threadIdx.x == 0) {
+    gp_result r;
+    memset(&r, 0, sizeof(r));
+    r.status = st;
+    a.res[g] = r;
+  }
+}
+
+__device__ void zero_ctrl(Ctrl* c) {
+  uint64_t* p = (uint64_t*)c;
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 8); i += blockDim.x) p[i] = 0;
+  __syncthreads();
+}
+
+// one graph, the whole workgroup; returns nothing, writes res[g] and part
+__device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsigned char* lds,
+                            SelShared* sel, RefCtl* srf) {
+  Ctrl* ctrl = ws.ctrl;
+  LevelRec* lev = ws.lev;
+  const Scratch& sc = ws.sc;
+  const int64_t v0 = a.voff[g], e0 = a.eoff[g];
+  const int32_t n = (int32_t)(a.voff[g + 1] - v0);
+  const int32_t nnz = (int32_t)(a.eoff[g + 1] - e0);
+  const int32_t* xadj = a.xadj + v0 + g;
+  const int32_t* adj = a.adj + e0;
+  const int64_t* w = a.w + e0;
+  const int64_t* vwgt = a.vwgt + 2 * v0;
+  zero_ctrl(ctrl);
+  if (n == 0) {
+    if (threadIdx.x == 0) {
+      gp_result r;
+      memset(&r, 0, sizeof(r));
+      r.feasible = 1;
+      a.res[g] = r;
+    }
+    return;
+  }
+  // ---- checks and canonical form (gp_create)
+  b_val_xadj(n, xadj, ctrl, 0, 1);
+  __syncthreads();
+  if (ctrl->verr & kVInval || xadj[n] != nnz) {
+    write_status(a, g, GP_EINVAL);
+    return;
+  }
+  int64_t* vc0 = (int64_t*)arena_alloc(a, 8ull * n);
+  int64_t* vg0 = (int64_t*)arena_alloc(a, 8ull * n);
+  if (!vc0 || !vg0) {
+    write_status(a, g, GP_ENOMEM);
+    return;
+  }
+  b_split_vwgt(n, vwgt, vc0, vg0, 0, 1);
+  __syncthreads();
+  b_val_rows(n, xadj, adj, w, vc0, vg0, ctrl, 0, 1);
+  __syncthreads();
+  uint32_t e = ctrl->verr;
+  if (e & kVRange) { write_status(a, g, GP_ERANGE); return; }
+  if (e & kVSelf) { write_status(a, g, GP_ESELF); return; }
+  const int32_t* adj0 = adj;
+  const int64_t* w0 = w;
+  if (ctrl->vunsorted) {
+    int32_t* na = (int32_t*)arena_alloc(a, 4ull * nnz);
+    int64_t* nw = (int64_t*)arena_alloc(a, 8ull * nnz);
+    if (!na || !nw) { write_status(a, g, GP_ENOMEM); return; }
+    b_sort_rows(n, xadj, adj, w, na, nw, ctrl, lds, 0, 1);
+    __syncthreads();
+    b_sort_long(n, xadj, adj, w, na, nw, ctrl, lds, 0, 1);
+    __syncthreads();
+    if (ctrl->verr & kVDup) { write_status(a, g, GP_EDUP); return; }
+    adj0 = na;
+    w0 = nw;
+  }
+  b_val_sym(n, xadj, adj0, w0, ctrl, 0, 1);
+  __syncthreads();
+  e = ctrl->verr;
+  if (e & kVAsym) { write_status(a, g, GP_EASYM); return; }
+  if (e & kVOverflow) { write_status(a, g, GP_EOVERFLOW); return; }
+  const int64_t W = (int64_t)(a.bal ? ctrl->vsum_g : ctrl->vsum_c);
+  const int64_t maxb0 = a.bal ? ctrl->vmax_g : ctrl->vmax_c;
+  __syncthreads();
+  // ---- balance bounds, Eq. (1)-(2) in integers
+  if (threadIdx.x == 0) {
+    const __int128 Rr = (__int128)a.r0 + a.r1;
+    const int64_t r[2] = {a.r0, a.r1};
+    for (int p = 0; p < 2; p++) {
+      ctrl->tgt[p] = (int64_t)(((__int128)W * r[p]) / Rr);
+      const __int128 num = (__int128)W * r[p] * (1000000 + a.eps);
+      const __int128 den = Rr * 1000000;
+      ctrl->ref.maxw[p] = (int64_t)((num + den - 1) / den);
+    }
+    ctrl->cap = (int64_t)(((__int128)3 * W + 2 * (__int128)a.C - 1) / (2 * (__int128)a.C));
+    ctrl->maxb = maxb0;
+    lev[0].n = n;
+    lev[0].nnz = nnz;
+    lev[0].xadj = xadj;
+    lev[0].adj = adj0;
+    lev[0].w = w0;
+    lev[0].vc = vc0;
+    lev[0].vg = vg0;
+  }
+  __syncthreads();
+  // ---- coarsening
+  int L = 0;
+  bool oom = false;
+  while (lev[L].n > a.C) {
+    const LevelRec f = lev[L];
+    int32_t* match = (int32_t*)arena_alloc(a, 4ull * f.n);
+    int32_t* cmap = (int32_t*)arena_alloc(a, 4ull * f.n);
+    int32_t* cxadj = (int32_t*)arena_alloc(a, 4ull * (f.n + 1));
+    int32_t* cadj = (int32_t*)arena_alloc(a, 4ull * f.nnz);
+    int64_t* cw = (int64_t*)arena_alloc(a, 8ull * f.nnz);
+    int64_t* cvc = (int64_t*)arena_alloc(a, 8ull * f.n);
+    int64_t* cvg = (int64_t*)arena_alloc(a, 8ull * f.n);
+    if (!match || !cmap || !cxadj || !cadj || !cw || !cvc || !cvg) {
+      oom = true;
+      break;
+    }
+    LevelView fv;
+    fv.n = f.n;
+    fv.nnz = f.nnz;
+    fv.xadj = f.xadj;
+    fv.adj = f.adj;
+    fv.w = f.w;
+    fv.b = a.bal ? f.vg : f.vc;
+    b_level_reset(ctrl, L > 0, 0, 1);
+    __syncthreads();
+    const int tw = team_width_dev(f.n, f.nnz);
+    uint64_t hs = mix64(a.seed ^ (uint64_t)(uint32_t)L);
+    for (int rr = 0; rr < a.R; rr++) {
+      TW_DISPATCH(tw, (b_match_propose<TWv>(fv, match, sc.prop, ctrl, rr, hs, 0, 1)));
+      __syncthreads();
+      b_match_resolve(f.n, match, sc.prop, ctrl, rr, 0, 1);
+      __syncthreads();
+    }
+    if (a.R == 0) {
+      for (int32_t u = threadIdx.x; u < f.n; u += blockDim.x) match[u] = -1;
+      __syncthreads();
+    }
+    TW_DISPATCH(tw, (b_hub<TWv>(fv, match, sc.prop, hs, 0, 1)));
+    __syncthreads();
+    TW_DISPATCH(tw, (b_twohop<TWv>(fv, sc.prop, match, ctrl, 0, 1)));
+    __syncthreads();
+    const int ntiles = (f.n + kTileV - 1) / kTileV;
+    b_iso_count(fv, match, ctrl, sc.tile_lead, ntiles, 0, 1);
+    __syncthreads();
+    b_iso_list(fv, match, sc.tile_lead, sc.longlist, ntiles, 0, 1);
+    __syncthreads();
+    b_iso_pair(fv.b, sc.longlist, match, ctrl, 0, 1);
+    __syncthreads();
+    b_contract_count(fv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles, 0, 1);
+    __syncthreads();
+    b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,
+                   sc.cmem1, sc.toff, ntiles, 0, 1);
+    __syncthreads();
+    const int ntc = (f.n + kTileC - 1) / kTileC;
+    b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
+                    sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1);
+    __syncthreads();
+    b_contract_long(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
+                    sc.tile_cnt, sc.longlist, ntc, lds, 0, 1);
+    __syncthreads();
+    b_contract_compact(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv, cxadj, cadj, cw, ntc,
+                       0, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      lev[L].match = match;
+      lev[L].cmap = cmap;
+      LevelRec c;
+      c.n = ctrl->nc;
+      c.nnz = ctrl->nnz_c;
+      c.xadj = cxadj;
+      c.adj = cadj;
+      c.w = cw;
+      c.vc = cvc;
+      c.vg = cvg;
+      lev[L + 1] = c;
+    }
+    __syncthreads();
+    L++;
+    if (20 * (int64_t)lev[L].n > 19 * (int64_t)lev[L - 1].n || L == kMaxLevels) break;
+  }
+  // assignment arrays of every level
+  for (int l = 0; l <= L && !oom; l++) {
+    int8_t* p = (int8_t*)arena_alloc(a, (uint64_t)lev[l].n);
+    if (!p) oom = true;
+    else if (threadIdx.x == 0) lev[l].part = p;
+    __syncthreads();
+  }
+  if (oom) {
+    write_status(a, g, GP_ENOMEM);
+    return;
+  }
+  // ---- initial bisection on the coarsest level
+  {
+    const LevelRec cl = lev[L];
+    LevelView cv;
+    cv.n = cl.n;
+    cv.nnz = cl.nnz;
+    cv.xadj = cl.xadj;
+    cv.adj = cl.adj;
+    cv.w = cl.w;
+    cv.b = a.bal ? cl.vg : cl.vc;
+    const int K = a.K < cl.n ? a.K : cl.n;
+    const int gs = a.r0 <= a.r1 ? 0 : 1;
+    b_init_tot(cv, ws.tot, 0, 1);
+    __syncthreads();
+    if (cl.n <= kTrialLdsMax) {
+      for (int t = 0; t < K; t++)
+        b_trial_lds<kBlock>(cv, ws.tot, K, t, gs, a.P, ctrl, ws.tctl, ws.tpart, ws.tres, lds, sel,
+                            srf);
+    } else {
+      const uint64_t kn = (uint64_t)K * cl.n;
+      int8_t* tp = (int8_t*)arena_alloc(a, kn);
+      int64_t* tc = (int64_t*)arena_alloc(a, 8 * kn);
+      int32_t* ta = (int32_t*)arena_alloc(a, 4 * kn);
+      Cand* tl = (Cand*)arena_alloc(a, sizeof(Cand) * kn);
+      if (!tp || !tc || !ta || !tl) {
+        write_status(a, g, GP_ENOMEM);
+        return;
+      }
+      for (int t = 0; t < K; t++)
+        b_trial_global<kBlock>(cv, ws.tot, K, t, gs, a.P, ctrl, ws.tctl, tp, tc, ta, tl, ws.tres,
+                               sel);
+      b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, tp, ws.tres, cl.part);
+    }
+    if (cl.n <= kTrialLdsMax) b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, ws.tpart, ws.tres, cl.part);
+    __syncthreads();
+  }
+  // ---- uncoarsening with refinement
+  for (int l = L - 1; l >= 0; l--) {
+    const LevelRec f = lev[l];
+    b_project(f.n, f.cmap, lev[l + 1].part, f.part, &ctrl->ref, a.P, 0, 1);
+    __syncthreads();
+    LevelView fv;
+    fv.n = f.n;
+    fv.nnz = f.nnz;
+    fv.xadj = f.xadj;
+    fv.adj = f.adj;
+    fv.w = f.w;
+    fv.b = a.bal ? f.vg : f.vc;
+    const int tw = team_width_dev(f.n, f.nnz);
+    for (int p = 0; p < a.P; p++) {
+      TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, 0, 1)));
+      __syncthreads();
+      b_refine_apply(f.part, &ctrl->ref, sc.list, ws.pass_sink, 0, 1);
+      __syncthreads();
+    }
+  }
+  // ---- result
+  const LevelRec l0 = lev[0];
+  LevelView v0w;
+  v0w.n = l0.n;
+  v0w.nnz = l0.nnz;
+  v0w.xadj = l0.xadj;
+  v0w.adj = l0.adj;
+  v0w.w = l0.w;
+  v0w.b = a.bal ? l0.vg : l0.vc;
+  b_clear_stats(ctrl, 0, 1);
+  __syncthreads();
+  const int tw0 = team_width_dev(l0.n, l0.nnz);
+  TW_DISPATCH(tw0, (b_final_stats<TWv>(v0w, l0.vc, l0.vg, l0.part, ctrl, 0, 1)));
+  __syncthreads();
+  int8_t* out = a.part + v0;
+  for (int32_t v = threadIdx.x; v < n; v += blockDim.x) out[v] = l0.part[v];
+  if (threadIdx.x == 0) {
+    gp_result r;
+    memset(&r, 0, sizeof(r));
+    r.cut = ctrl->res_ext / 2;
+    r.load[0] = ctrl->res_load[0];
+    r.load[1] = ctrl->res_load[1];
+    r.time[0] = ctrl->res_time[0];
+    r.time[1] = ctrl->res_time[1];
+    r.feasible = (r.load[0] <= ctrl->ref.maxw[0] && r.load[1] <= ctrl->ref.maxw[1]) ? 1 : 0;
+    r.levels = L;
+    r.used_learned = 0;
+    r.status = GP_OK;
+    a.res[g] = r;
+  }
+  __syncthreads();
+}
+
+constexpr size_t kBatchLds = 64 * 1024 - 6 * 1024;  // dynamic LDS of the persistent kernel
+
+__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ SelShared sel;
+  __shared__ RefCtl srf;
+  __shared__ int s_next;
+  const WgScratch ws = wg_scratch(a);
+  for (;;) {
+    if (threadIdx.x == 0) s_next = (int)atomicAdd(a.head, (uint32_t)a.chunk);
+    __syncthreads();
+    const int first = s_next;
+    __syncthreads();
+    if (first >= a.G) break;
+    const int last = first + a.chunk < a.G ? first + a.chunk : a.G;
+    for (int i = first; i < last; i++) batch_graph(a, a.order[i], ws, lds, &sel, &srf);
+  }
+}
+
+__global__ void k_batch_reset(uint32_t* head, unsigned long long* arena_off) {
+  if (threadIdx.x == 0) {
+    *head = 0;
+    *arena_off = 0;
+  }
+}
+
+}  // namespace gpk
+
+// ===================================================================== host
+using namespace gpk;
+
+namespace {
+
+template <class T>
+struct HBuf {  // device buffer
+  T* p = nullptr;
+  size_t cap = 0;
+  bool ensure(size_t n) {
+    if (n == 0) n = 1;
+    if (p && n <= cap) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc((void**)&p, n * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return false;
+    }
+    cap = n;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+}  // namespace
+
+struct gp_batch {
+  hipStream_t stream = nullptr;
+  int nwg = 0;          // persistent workgroups (0: 2 per compute unit)
+  int chunk = 1;        // graphs per queue pop
+  int order_mode = 0;   // 0: largest first, 1: input order
+  HBuf<unsigned char> wgs, arena;
+  HBuf<int32_t> order;
+  HBuf<gp_result> res;
+  HBuf<uint32_t> head;
+  HBuf<unsigned long long> arena_off;
+  gp_result* hres = nullptr;  // pinned
+  size_t hres_cap = 0;
+  int64_t* hoff = nullptr;    // pinned voff | eoff
+  size_t hoff_cap = 0;
+  double arena_factor = 3.0;
+  // captured launch
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchArgs cached;
+  int cached_nwg = 0;
+  bool have_exec = false;
+  int cus = 0;
+  ~gp_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    wgs.release(); arena.release(); order.release(); res.release(); head.release();
+    arena_off.release();
+    if (hres) (void)hipHostFree(hres);
+    if (hoff) (void)hipHostFree(hoff);
+  }
+};
+
+static gp_status batch_options(const gp_options* o) {
+  if (!o) return GP_EINVAL;
+  const int64_t lim = (int64_t)1 << 40;
+  if (o->ratio[0] < 0 || o->ratio[1] < 0 || o->ratio[0] >= lim || o->ratio[1] >= lim ||
+      o->ratio[0] + o->ratio[1] == 0)
+    return GP_EINVAL;
+  if (o->eps_ppm < 0 || o->eps_ppm > 1000000 || (o->balance_on != 0 && o->balance_on != 1))
+    return GP_EINVAL;
+  if (o->coarsen_to < 1 || o->match_rounds < 0 || o->match_rounds > kMaxRounds ||
+      o->refine_passes < 0 || o->refine_passes > 64 || o->init_trials < 1 || o->init_trials > 64)
+    return GP_EINVAL;
+  if (o->flags & GP_LEARNED) return GP_EMODEL;
+  return GP_OK;
+}
+
+static bool same_args(const BatchArgs& x, const BatchArgs& y) {
+  return memcmp(&x, &y, sizeof(BatchArgs)) == 0;
+}
+
+// runs the persistent kernel once for the graphs in a.order[0..a.G)
+static gp_status batch_launch(gp_batch* b, BatchArgs a, int nwg) {
+  hipStream_t s = b->stream;
+  const size_t dyn = kBatchLds;
+  if (!b->have_exec || !same_args(a, b->cached) || nwg != b->cached_nwg) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->have_exec = false;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GP_EDEVICE;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      k_batch_reset<<<1, 64, 0, cs>>>(a.head, a.arena_off);
+      k_batch<<<nwg, kBlock, dyn, cs>>>(a);
+      ok = hipStreamEndCapture(cs, &b->graph) == hipSuccess;
+    }
+    (void)hipStreamDestroy(cs);
+    if (!ok || hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return GP_EDEVICE;
+    }
+    b->cached = a;
+    b->cached_nwg = nwg;
+    b->have_exec = true;
+  }
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return GP_EDEVICE;
+  }
+  return GP_OK;
+}
+
+extern "C" {
+
+gp_status gp_batch_create(gp_batch** out, void* stream) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  gp_batch* b = new (std::nothrow) gp_batch();
+  if (!b) return GP_ENOMEM;
+  b->stream = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete b;
+    return GP_EDEVICE;
+  }
+  if (hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kBatchLds) != hipSuccess)
+    (void)hipGetLastError();
+  *out = b;
+  return GP_OK;
+}
+
+void gp_batch_destroy(gp_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode) {
+  if (!b || workgroups < 0 || chunk < 1 || chunk > 64 || order_mode < 0 || order_mode > 1)
+    return GP_EINVAL;
+  b->nwg = workgroups;
+  b->chunk = chunk;
+  b->order_mode = order_mode;
+  return GP_OK;
+}
+
+gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
+                             const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
+                             const int64_t* vwgt, const gp_options* o, int8_t* part,
+                             gp_result* res) {
+  if (!b || G < 0 || (G > 0 && (!voff || !eoff || !xadj || !vwgt || !part || !res)))
+    return GP_EINVAL;
+  gp_status st = batch_options(o);
+  if (st != GP_OK) return st;
+  if (G == 0) return GP_OK;
+  hipStream_t s = b->stream;
+  // offsets to the host
+  const size_t need = 2 * ((size_t)G + 1);
+  if (b->hoff_cap < need) {
+    if (b->hoff) (void)hipHostFree(b->hoff);
+    b->hoff = nullptr;
+    b->hoff_cap = 0;
+    if (hipHostMalloc((void**)&b->hoff, need * sizeof(int64_t), hipHostMallocDefault) !=
+        hipSuccess)
+      return GP_ENOMEM;
+    b->hoff_cap = need;
+  }
+  int64_t* hv = b->hoff;
+  int64_t* he = b->hoff + G + 1;
+  if (hipMemcpyAsync(hv, voff, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(he, eoff, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GP_EDEVICE;
+  if (hv[0] != 0 || he[0] != 0) return GP_EINVAL;
+  int64_t nmax = 0, nnzmax = 0;
+  for (int g = 0; g < G; g++) {
+    const int64_t ng = hv[g + 1] - hv[g], mg = he[g + 1] - he[g];
+    if (ng < 0 || mg < 0 || ng > INT32_MAX || mg > INT32_MAX) return GP_EINVAL;
+    nmax = ng > nmax ? ng : nmax;
+    nnzmax = mg > nnzmax ? mg : nnzmax;
+  }
+  const int64_t ntot = hv[G], mtot = he[G];
+  if ((ntot > 0 && !adjncy && mtot > 0) || (mtot > 0 && !adjwgt)) return GP_EINVAL;
+  // processing order: largest graphs first (or input order)
+  std::vector<int32_t> ord(G);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (b->order_mode == 0)
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return (he[x + 1] - he[x]) + (hv[x + 1] - hv[x]) > (he[y + 1] - he[y]) + (hv[y + 1] - hv[y]);
+    });
+  const int nwg = b->nwg > 0 ? b->nwg : 2 * (b->cus > 0 ? b->cus : 256);
+  uint64_t offs[32];
+  const uint64_t stride = wg_layout((int32_t)nmax, (int32_t)nnzmax, offs);
+  const uint64_t arena_bytes =
+      (uint64_t)(b->arena_factor * (double)(ntot * 57 + mtot * 12)) + (uint64_t)G * 8192 + (1 << 20);
+  if (!b->wgs.ensure((size_t)stride * nwg) || !b->arena.ensure(arena_bytes) ||
+      !b->order.ensure(G) || !b->res.ensure(G) || !b->head.ensure(1) || !b->arena_off.ensure(1))
+    return GP_ENOMEM;
+  if (b->hres_cap < (size_t)G) {
+    if (b->hres) (void)hipHostFree(b->hres);
+    b->hres = nullptr;
+    b->hres_cap = 0;
+    if (hipHostMalloc((void**)&b->hres, sizeof(gp_result) * G, hipHostMallocDefault) != hipSuccess)
+      return GP_ENOMEM;
+    b->hres_cap = G;
+  }
+  if (hipMemcpyAsync(b->order.p, ord.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return GP_EDEVICE;
+  BatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.G = G;
+  a.voff = voff;
+  a.eoff = eoff;
+  a.xadj = xadj;
+  a.adj = adjncy;
+  a.w = adjwgt;
+  a.vwgt = vwgt;
+  a.order = b->order.p;
+  a.part = part;
+  a.res = b->res.p;
+  a.r0 = o->ratio[0];
+  a.r1 = o->ratio[1];
+  a.eps = o->eps_ppm;
+  a.bal = o->balance_on;
+  a.seed = o->seed;
+  a.C = o->coarsen_to;
+  a.R = o->match_rounds;
+  a.P = o->refine_passes;
+  a.K = o->init_trials;
+  a.head = b->head.p;
+  a.arena = b->arena.p;
+  a.arena_cap = b->arena.cap;
+  a.arena_off = b->arena_off.p;
+  a.wgs = b->wgs.p;
+  a.wgs_stride = stride;
+  a.nmax = (int32_t)nmax;
+  a.nnzmax = (int32_t)nnzmax;
+  a.chunk = b->chunk;
+  if ((st = batch_launch(b, a, nwg)) != GP_OK) return st;
+  if (hipMemcpyAsync(b->hres, b->res.p, sizeof(gp_result) * G, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GP_EDEVICE;
+  // graphs that ran out of arena: rerun them alone with a larger arena
+  for (int attempt = 0; attempt < 4; attempt++) {
+    std::vector<int32_t> redo;
+    for (int g = 0; g < G; g++)
+      if (b->hres[g].status == GP_ENOMEM) redo.push_back(g);
+    if (redo.empty()) break;
+    b->arena_factor *= 2.0;
+    const uint64_t nb = (uint64_t)(b->arena_factor * (double)(ntot * 57 + mtot * 12)) +
+                        (uint64_t)G * 8192 + (1 << 20);
+    if (!b->arena.ensure(nb)) return GP_ENOMEM;
+    if (hipMemcpyAsync(b->order.p, redo.data(), sizeof(int32_t) * redo.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+      return GP_EDEVICE;
+    BatchArgs a2 = a;
+    a2.G = (int32_t)redo.size();
+    a2.arena = b->arena.p;
+    a2.arena_cap = b->arena.cap;
+    if ((st = batch_launch(b, a2, nwg)) != GP_OK) return st;
+    if (hipMemcpyAsync(b->hres, b->res.p, sizeof(gp_result) * G, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GP_EDEVICE;
+  }
+  memcpy(res, b->hres, sizeof(gp_result) * G);
+  return GP_OK;
+}
+
+}  // extern "C"

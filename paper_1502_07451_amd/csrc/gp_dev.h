@@ -133,6 +133,17 @@ __device__ __forceinline__ bool last_block(uint32_t* ctr, uint32_t nblocks) {
   return last;
 }
 
+// Tail of a phase that runs on nblk blocks: true in the block that runs the
+// phase's single-block tail.  With one block it is that block, after a
+// barrier; otherwise the last block to finish (see last_block).
+__device__ __forceinline__ bool tail_gate(uint32_t* ctr, int nblk) {
+  if (nblk == 1) {
+    __syncthreads();
+    return true;
+  }
+  return last_block(ctr, (uint32_t)nblk);
+}
+
 // Appends c to list when flag is set, one atomic per wave.  The order of
 // the list is unspecified; every consumer of it is order-independent.
 __device__ __forceinline__ void append_cand(bool flag, const Cand& c, Cand* list,
@@ -164,15 +175,47 @@ struct SelShared {
   u128 result;
 };
 
-// Radix descent over the candidate list (8-bit digits from the top).
+// Candidate sources for the threshold search: a compacted list, or every
+// vertex of an LDS-resident graph filtered by the pass predicate.
+struct ListItems {
+  const Cand* list;
+  uint32_t n;
+  __device__ __forceinline__ uint32_t count() const { return n; }
+  __device__ __forceinline__ bool get(uint32_t i, Cand& c) const {
+    c = list[i];
+    return true;
+  }
+};
+
+struct LdsItems {
+  const int64_t* gain;
+  const int64_t* b;
+  const int8_t* part;
+  int32_t n;
+  int s, mode;
+  __device__ __forceinline__ uint32_t count() const { return (uint32_t)n; }
+  __device__ __forceinline__ bool get(uint32_t i, Cand& c) const {
+    if (part[i] != s) return false;
+    const int64_t g = gain[i];
+    if (mode == 0 && g <= 0) return false;
+    c.gain = g;
+    c.b = b[i];
+    c.v = (int32_t)i;
+    c.pad = 0;
+    return true;
+  }
+};
+
+// Radix descent over the candidates (8-bit digits from the top).
 //   want_ge = 0: threshold of the longest prefix with weight <= bound
 //   want_ge = 1: threshold of the shortest prefix with weight >= bound (> 0)
 // Returns thr with the prefix = { key >= thr }.  Every thread of the block
 // must call it; BS is the block size.
-template <int BS>
-__device__ u128 select_prefix(const Cand* list, uint32_t ncand, int64_t gmin, int idbits,
-                              int tbits, int want_ge, int64_t bound, SelShared* sh) {
+template <int BS, class Items>
+__device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int tbits,
+                              int want_ge, int64_t bound, SelShared* sh) {
   const int ndig = (tbits + 7) / 8;
+  const uint32_t cnt = items.count();
   if (threadIdx.x == 0) {
     sh->prefix = 0;
     sh->above = 0;
@@ -185,8 +228,9 @@ __device__ u128 select_prefix(const Cand* list, uint32_t ncand, int64_t gmin, in
     for (int i = threadIdx.x; i < 256; i += BS) sh->hist[i] = 0;
     __syncthreads();
     const u128 P = sh->prefix;
-    for (uint32_t i = threadIdx.x; i < ncand; i += BS) {
-      Cand c = list[i];
+    for (uint32_t i = threadIdx.x; i < cnt; i += BS) {
+      Cand c;
+      if (!items.get(i, c)) continue;
       u128 k = cand_key(c, gmin, idbits);
       if ((k >> (shf + 8)) == P)
         atomicAdd((unsigned long long*)&sh->hist[(int)((k >> shf) & 255)],
@@ -342,6 +386,76 @@ __device__ int block_sort_emit(int L, const Loader& ld, int32_t* sk, int64_t* sv
     }
   }
   __syncthreads();
+  return total;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 64 < L <= kWaveCap, one wave, LDS arrays sk/sv private to the wave
+template <bool MERGE, class Loader>
+__device__ int wave_sort_emit(int L, const Loader& ld, int32_t* sk, int64_t* sv, int32_t* okey,
+                              int64_t* oval, bool* dup) {
+  const int lane = lane_id();
+  const int P2 = next_pow2(L);
+  for (int i = lane; i < P2; i += 64) {
+    int32_t k = INT_MAX;
+    int64_t v = 0;
+    if (i < L) ld(i, k, v);
+    sk[i] = k;
+    sv[i] = v;
+  }
+  wave_sync();
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < P2 / 2; i += 64) {
+        const int lo = (i / stride) * stride * 2 + (i % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int32_t a = sk[lo], b = sk[hi];
+        if ((a > b) == up && a != b) {
+          sk[lo] = b;
+          sk[hi] = a;
+          const int64_t t = sv[lo];
+          sv[lo] = sv[hi];
+          sv[hi] = t;
+        }
+      }
+      wave_sync();
+    }
+  }
+  const int per = P2 / 64;  // P2 >= 128 here
+  const int s0 = lane * per;
+  int heads = 0;
+  for (int i = s0; i < s0 + per; i++) {
+    if (sk[i] == INT_MAX) break;
+    if (i == 0 || sk[i - 1] != sk[i]) heads++;
+    else if (!MERGE) *dup = true;
+  }
+  int x = heads;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  const int total = __shfl(x, 63, 64);
+  int base = x - heads;
+  for (int i = s0; i < s0 + per; i++) {
+    const int32_t k = sk[i];
+    if (k == INT_MAX) break;
+    if (i == 0 || sk[i - 1] != k) {
+      int64_t sum = sv[i];
+      if (MERGE)
+        for (int j = i + 1; j < P2 && sk[j] == k; j++) sum += sv[j];
+      okey[base] = k;
+      oval[base] = sum;
+      base++;
+    }
+  }
+  wave_sync();
   return total;
 }
 

@@ -5,6 +5,8 @@
 // partitions of one handle allocate nothing after the first call.  Work is
 // queued on the handle's stream; the host waits only once per coarse level
 // (to learn the coarse graph's size) and once at the end.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -98,6 +100,10 @@ struct gp_graph {
   DBuf<Cand> i_list;
   Ctrl* ctrl = nullptr;
   Ctrl* hctrl = nullptr;  // pinned
+  // profiling
+  bool profiling = false;
+  Prof prof;
+  std::vector<gp_prof_row> prof_rows;
 
   Scratch scratch() const {
     Scratch s;
@@ -150,6 +156,10 @@ struct gp_graph {
     i_adjc.release(); i_list.release();
     if (ctrl) (void)hipFree(ctrl);
     if (hctrl) (void)hipHostFree(hctrl);
+    for (int i = 0; i < prof.npool; i++)
+      if (prof.pool[i]) (void)hipEventDestroy(prof.pool[i]);
+    free(prof.pool);
+    free(prof.recs);
   }
 };
 
@@ -170,6 +180,55 @@ static gp_status read_ctrl(gp_graph* g) {
   HIPCHK(hipMemcpyAsync(g->hctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
   return GP_OK;
+}
+
+// marks which recorded launches of a level did their work
+static void prof_mark(gp_graph* g, int level, bool coarsening) {
+  if (!g->profiling) return;
+  const Ctrl& h = *g->hctrl;
+  for (int i = 0; i < g->prof.nrec; i++) {
+    ProfRec& r = g->prof.recs[i];
+    if (r.level != level) continue;
+    if (coarsening && (r.kind == PK_MATCH_PROPOSE || r.kind == PK_MATCH_RESOLVE))
+      r.executed = (r.idx == 0 || h.made[r.idx - 1] > 0) ? 1 : 0;
+    if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_APPLY))
+      r.executed = r.idx < h.lvl_pass[level] ? 1 : 0;
+  }
+}
+
+// folds the recorded launches of one call into the per-kernel rows
+static void prof_collect(gp_graph* g) {
+  Prof& p = g->prof;
+  for (int i = 0; i < p.nrec; i++) {
+    const ProfRec& r = p.recs[i];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 0.f;
+    }
+    char name[40];
+    if (r.tw > 0) snprintf(name, sizeof(name), "%s<%d>", kProfNames[r.kind], r.tw);
+    else snprintf(name, sizeof(name), "%s", kProfNames[r.kind]);
+    gp_prof_row* row = nullptr;
+    for (auto& x : g->prof_rows)
+      if (strcmp(x.name, name) == 0) row = &x;
+    if (!row) {
+      gp_prof_row z;
+      memset(&z, 0, sizeof(z));
+      snprintf(z.name, sizeof(z.name), "%s", name);
+      g->prof_rows.push_back(z);
+      row = &g->prof_rows.back();
+    }
+    row->launches++;
+    row->ms += ms;
+    if (r.executed) {
+      row->executed++;
+      row->bytes += r.bytes;
+    }
+  }
+  p.nrec = 0;
+  p.used = 0;
+  p.failed = false;
 }
 
 static gp_status check_options(const gp_options* o) {
@@ -372,8 +431,23 @@ gp_status gp_create(gp_graph** out, int32_t n, const int32_t* xadj, const int32_
   return GP_OK;
 }
 
+static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* part,
+                                     gp_result* res, int64_t* trace, int32_t trace_cap);
+
 static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
                                int64_t* trace, int32_t trace_cap) {
+  if (g && g->profiling) g_prof = &g->prof;
+  gp_status st = run_partition_inner(g, o, part, res, trace, trace_cap);
+  if (g && g->profiling) {
+    (void)hipStreamSynchronize(g->stream);
+    prof_collect(g);
+    g_prof = nullptr;
+  }
+  return st;
+}
+
+static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* part,
+                                     gp_result* res, int64_t* trace, int32_t trace_cap) {
   if (!g || !res || (g->n > 0 && !part)) return GP_EINVAL;
   gp_status st = check_options(o);
   if (st != GP_OK) return st;
@@ -421,13 +495,18 @@ static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, g
     const int tw = team_width_for(f->n, f->nnz);
     const uint64_t hs = host_mix64(o->seed ^ (uint64_t)(uint32_t)L);
     if (R == 0) HIPCHK(hipMemsetAsync(f->match.p, 0xff, sizeof(int32_t) * f->n, s));
-    for (int rr = 0; rr < R; rr++)
+    g->prof.level = L;
+    for (int rr = 0; rr < R; rr++) {
+      g->prof.idx = rr;
       LCHK(launch_match_round(fv, f->match.p, sc.prop, g->ctrl, rr, hs, tw, s));
+    }
+    g->prof.idx = 0;
     LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));
     LCHK(launch_contract_b(fv, f->cmap.p, g->ctrl, sc, f->n, c->xadj.p, c->adj.p, c->w.p, s));
     if ((st = read_ctrl(g)) != GP_OK) return st;
+    prof_mark(g, L, true);
     c->n = h.nc;
     c->nnz = h.nnz_c;
     pairs[L] = (int64_t)f->n - c->n;
@@ -440,6 +519,7 @@ static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, g
     const int K = o->init_trials < cl->n ? o->init_trials : cl->n;
     if (!g->ensure_init(cl->n, K)) return GP_ENOMEM;
     const int gs = o->ratio[0] <= o->ratio[1] ? 0 : 1;
+    g->prof.level = L;
     LCHK(launch_init(cl->view(bal), K, gs, P, g->ctrl, g->init_scratch(), cl->part.p, s));
   }
   auto record = [&](int l, bool coarsest) -> gp_status {
@@ -464,10 +544,16 @@ static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, g
   for (int l = L - 1; l >= 0; l--) {
     Level* f = g->lv[l];
     Level* c = g->lv[l + 1];
+    g->prof.level = l;
+    g->prof.idx = 0;
     LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, s));
     const int tw = team_width_for(f->n, f->nnz);
     const LevelView fv = f->view(bal);
-    for (int p = 0; p < P; p++) LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, tw, s));
+    for (int p = 0; p < P; p++) {
+      g->prof.idx = p;
+      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, tw,
+                              &g->ctrl->lvl_pass[l], s));
+    }
     if ((st = record(l, false)) != GP_OK) return st;
   }
   Level* l0 = g->lv[0];
@@ -477,6 +563,7 @@ static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, g
       (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   HIPCHK(hipMemcpyAsync(part, l0->part.p, (size_t)n, kout, s));
   if ((st = read_ctrl(g)) != GP_OK) return st;
+  for (int l = L - 1; l >= 0; l--) prof_mark(g, l, false);
   r.cut = h.res_ext / 2;
   r.load[0] = h.res_load[0];
   r.load[1] = h.res_load[1];
@@ -485,8 +572,23 @@ static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, g
   r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
   r.levels = L;
   r.used_learned = 0;
+  r.status = GP_OK;
   *res = r;
   return GP_OK;
+}
+
+gp_status gp_profile_enable(gp_graph* g, int32_t on) {
+  if (!g) return GP_EINVAL;
+  g->profiling = on != 0;
+  return GP_OK;
+}
+
+int32_t gp_profile_read(gp_graph* g, gp_prof_row* rows, int32_t cap, int32_t reset) {
+  if (!g || (cap > 0 && !rows)) return -1;
+  const int32_t n = (int32_t)g->prof_rows.size();
+  for (int32_t i = 0; i < n && i < cap; i++) rows[i] = g->prof_rows[i];
+  if (reset) g->prof_rows.clear();
+  return n;
 }
 
 gp_status gp_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res) {

@@ -13,7 +13,9 @@ namespace gpk {
 
 constexpr int kBlock = 256;       // threads per block of the level kernels
 constexpr int kTileV = 1024;      // vertices per tile of the ordered-scan kernels
-constexpr int kTileC = 256;       // coarse rows per tile of the row-sort kernel
+constexpr int kTileC = 64;        // coarse rows per tile of the row-sort kernel
+constexpr int kWaveCap = 512;     // longest candidate row sorted in LDS by one wave
+constexpr int kRowBlockCap = 2048;  // longest candidate row sorted in LDS by one block (contraction)
 constexpr int kSortCap = 4096;    // longest candidate row sorted in LDS by one block
 constexpr int kWin = 4096;        // id window of the dense long-row merge
 constexpr int kMaxLevels = 48;
@@ -65,6 +67,7 @@ struct Ctrl {
   uint32_t ctr_count, ctr_long, ctr_stats, ctr_init;
   int32_t niso;           // unmatched vertices without neighbours
   uint32_t ctr_iso;
+  int32_t lvl_pass[kMaxLevels + 1];  // refinement passes run on each level
   // result of the final statistics kernel
   int64_t res_ext, res_load[2], res_time[2];
   // validation

@@ -34,6 +34,39 @@ struct InitScratch {
 
 int team_width_for(int32_t n, int64_t nnz);
 
+// ---- per-launch profiling (HIP events), enabled by the driver for one call
+enum ProfKind {
+  PK_MATCH_PROPOSE, PK_MATCH_RESOLVE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
+  PK_CONTRACT_MAP, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_COMPACT, PK_INIT_TOT,
+  PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_APPLY, PK_PROJECT, PK_FINAL_STATS, PK_N
+};
+extern const char* const kProfNames[PK_N];
+
+struct ProfRec {
+  int kind, tw, level, idx;   // idx: matching round or refinement pass
+  double bytes;               // algorithmic bytes if the launch does its work (0: undefined)
+  hipEvent_t a, b;
+  int executed;
+};
+
+struct Prof {
+  ProfRec* recs = nullptr;
+  int nrec = 0, cap = 0;
+  hipEvent_t* pool = nullptr;
+  int npool = 0, used = 0;
+  int level = 0, idx = 0;
+  bool failed = false;
+};
+extern Prof* g_prof;   // set by the driver around a profiled call (one host thread)
+
+// records events around one launch when profiling is on
+struct ProfScope {
+  ProfRec* r = nullptr;
+  hipStream_t s;
+  ProfScope(int kind, int tw, double bytes, hipStream_t st);
+  ~ProfScope();
+};
+
 bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s);
 bool launch_match_round(const LevelView& lv, int32_t* match, int32_t* prop, Ctrl* ctrl, int round,
                         uint64_t hs, int tw, hipStream_t s);
@@ -46,7 +79,7 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
                        int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
                        hipStream_t s);
 bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list, int tw,
-                        hipStream_t s);
+                        int32_t* pass_out, hipStream_t s);
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
                     int npass, hipStream_t s);
 bool launch_start_level(RefCtl* rc, int npass, hipStream_t s);

@@ -1,0 +1,1413 @@
+// gp_phases.h - device bodies of every phase of the partition pipeline.
+//
+// Each body b_X(..., bid, nblk) does the work of block bid out of nblk
+// blocks.  The single-graph path launches each body as its own kernel over
+// many blocks (gp_kernels.hip); the batched path calls the same bodies with
+// (0, 1) from inside one persistent kernel, one workgroup per graph
+// (gp_batch.hip).  A phase with a single-block tail runs it in the last
+// block to finish (tail_gate).  Large LDS buffers are passed in by the
+// caller so that one kernel can run several phases.
+#pragma once
+
+#include <stdlib.h>
+
+#include "gp_dev.h"
+
+namespace gpk {
+
+
+// ------------------------------------------------------------------ helpers
+// clears the per-level coarsening counters; on levels below the input graph
+// the largest balance weight measured by the previous contraction becomes
+// the current one
+__device__ __forceinline__ void b_level_reset(Ctrl* ctrl, int promote, int bid_, int nblk_) {
+  for (int i = threadIdx.x; i < kMaxRounds; i += blockDim.x) ctrl->made[i] = 0;
+  if (threadIdx.x == 0) {
+    if (promote) ctrl->maxb = ctrl->maxb_next;
+    ctrl->nc = 0;
+    ctrl->nnz_c = 0;
+    ctrl->nlong = 0;
+    ctrl->ubtot = 0;
+    ctrl->maxb_next = 0;
+  }
+}
+
+// ----------------------------------------------------------------- matching
+// Edge order for matching: heavier first, then larger hash of the endpoint
+// pair, then smaller endpoints.  For a fixed u, comparing (lo, hi) reduces
+// to comparing the neighbour id v.
+struct MatchBest {
+  int64_t w;   // -1: none
+  int32_t v;
+};
+
+__device__ __forceinline__ uint64_t pair_hash(uint64_t hs, int32_t u, int32_t v) {
+  uint32_t lo = (uint32_t)(u < v ? u : v), hi = (uint32_t)(u < v ? v : u);
+  return mix64(hs ^ (((uint64_t)lo << 32) | (uint64_t)hi));
+}
+
+// true when candidate (w, v) beats best (bw, bv) for vertex u
+__device__ __forceinline__ bool match_better(int64_t w, int32_t v, int64_t bw, int32_t bv,
+                                             uint64_t hs, int32_t u) {
+  if (bv < 0) return v >= 0;
+  if (v < 0) return false;
+  if (w != bw) return w > bw;
+  uint64_t h = pair_hash(hs, u, v), bh = pair_hash(hs, u, bv);
+  if (h != bh) return h > bh;
+  return v < bv;
+}
+
+template <int TW>
+__device__ __forceinline__ void b_match_propose(LevelView lv, const int32_t* match,
+                                                          int32_t* prop, const Ctrl* ctrl,
+                                                          int round, uint64_t hs, int bid_, int nblk_) {
+  if (round > 0 && ctrl->made[round - 1] == 0) return;
+  const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t uu = team; uu < lv.n; uu += nteams) {
+    const int32_t u = (int32_t)uu;
+    if (round > 0 && match[u] != -1) continue;
+    const int64_t bu = lv.b[u];
+    const bool capcheck = bu + maxb > cap;
+    int64_t bw = -1;
+    int32_t bv = -1;
+    const int32_t e1 = lv.xadj[u + 1];
+    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
+      const int32_t v = lv.adj[e];
+      if (round > 0 && match[v] != -1) continue;
+      if (capcheck && bu + lv.b[v] > cap) continue;
+      const int64_t w = lv.w[e];
+      if (match_better(w, v, bw, bv, hs, u)) {
+        bw = w;
+        bv = v;
+      }
+    }
+#pragma unroll
+    for (int o = TW / 2; o > 0; o >>= 1) {
+      int64_t ow = __shfl_xor(bw, o, TW);
+      int32_t ov = __shfl_xor(bv, o, TW);
+      if (match_better(ow, ov, bw, bv, hs, u)) {
+        bw = ow;
+        bv = ov;
+      }
+    }
+    if (lane == 0) prop[u] = bv;
+  }
+}
+
+__device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
+                                                          const int32_t* prop, Ctrl* ctrl,
+                                                          int round, int bid_, int nblk_) {
+  if (round > 0 && ctrl->made[round - 1] == 0) return;
+  __shared__ int32_t sm[kBlock / 64];
+  int32_t made = 0;
+  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
+       u += (int64_t)nblk_ * kBlock) {
+    if (round == 0) {
+      const int32_t p = prop[u];
+      const int32_t m = (p >= 0 && prop[p] == (int32_t)u) ? p : -1;
+      match[u] = m;
+      made += m >= 0;
+    } else if (match[u] == -1) {
+      const int32_t p = prop[u];
+      if (p >= 0 && prop[p] == (int32_t)u) {
+        match[u] = p;
+        made++;
+      }
+    }
+  }
+  made = block_sum<kBlock, int32_t>(made, sm);
+  if (threadIdx.x == 0 && made) atomicAdd(&ctrl->made[round], made);
+}
+
+// --------------------------------------------------------------- two-hop pass
+// hub[u] = first neighbour of an unmatched u under the edge order (-1: none);
+// matched vertices get -2
+template <int TW>
+__device__ __forceinline__ void b_hub(LevelView lv, const int32_t* match, int32_t* hub,
+                                                uint64_t hs, int bid_, int nblk_) {
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t uu = team; uu < lv.n; uu += nteams) {
+    const int32_t u = (int32_t)uu;
+    if (match[u] != -1) {
+      if (lane == 0) hub[u] = -2;
+      continue;
+    }
+    int64_t bw = -1;
+    int32_t bv = -1;
+    const int32_t e1 = lv.xadj[u + 1];
+    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
+      const int32_t v = lv.adj[e];
+      const int64_t w = lv.w[e];
+      if (match_better(w, v, bw, bv, hs, u)) {
+        bw = w;
+        bv = v;
+      }
+    }
+#pragma unroll
+    for (int o = TW / 2; o > 0; o >>= 1) {
+      int64_t ow = __shfl_xor(bw, o, TW);
+      int32_t ov = __shfl_xor(bv, o, TW);
+      if (match_better(ow, ov, bw, bv, hs, u)) {
+        bw = ow;
+        bv = ov;
+      }
+    }
+    if (lane == 0) hub[u] = bv;
+  }
+}
+
+// The members of h's group are the x in row h with hub[x] == h; the sorted
+// row lists them in ascending id.  They are paired first-second,
+// third-fourth, ... when the pair fits under the cap.  Each unmatched vertex
+// has one hub, so every match[] entry is written by one team only.
+template <int TW>
+__device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub,
+                                                   int32_t* match, const Ctrl* ctrl, int bid_, int nblk_) {
+  const int64_t cap = ctrl->cap;
+  const int lane = threadIdx.x & (TW - 1);
+  const int tb = lane_id() & ~(TW - 1);
+  const uint64_t tmask = TW == 64 ? ~0ull : ((1ull << TW) - 1ull);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t hh = team; hh < lv.n; hh += nteams) {
+    const int32_t h = (int32_t)hh;
+    const int32_t e1 = lv.xadj[h + 1];
+    int32_t pending = -1;
+    for (int32_t e0 = lv.xadj[h]; e0 < e1; e0 += TW) {
+      const int32_t e = e0 + lane;
+      const int32_t x = e < e1 ? lv.adj[e] : -1;
+      const bool mem = x >= 0 && hub[x] == h;
+      const uint64_t mask = (__ballot(mem) >> tb) & tmask;
+      const int k = __popcll(mask & below);
+      const int cnt = __popcll(mask);
+      const int off = pending >= 0 ? 1 : 0;
+      const uint64_t lower = mask & below;
+      const int prev_lane = lower ? 63 - __clzll(lower) : lane;
+      const int32_t prev_x = __shfl(x, prev_lane, TW);
+      const int last_lane = mask ? 63 - __clzll(mask) : 0;
+      const int32_t last_x = __shfl(x, last_lane, TW);
+      if (mem && ((k + off) & 1)) {
+        const int32_t y = k == 0 ? pending : prev_x;
+        if (lv.b[x] + lv.b[y] <= cap) {
+          match[x] = y;
+          match[y] = x;
+        }
+      }
+      if ((off + cnt) & 1) pending = cnt > 0 ? last_x : pending;
+      else pending = -1;
+    }
+  }
+}
+
+// unmatched vertices without neighbours, paired in ascending id
+__device__ __forceinline__ void b_iso_count(LevelView lv, const int32_t* match,
+                                                      Ctrl* ctrl, int32_t* tile_cnt,
+                                                      int ntiles, int bid_, int nblk_) {
+  __shared__ int32_t smi[kBlock / 64];
+  for (int t = bid_; t < ntiles; t += nblk_) {
+    int32_t c = 0;
+    const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
+    for (int j = 0; j < 4; j++) {
+      const int64_t u = base + j;
+      if (u < lv.n && match[u] == -1 && lv.xadj[u + 1] == lv.xadj[u]) c++;
+    }
+    c = block_sum<kBlock, int32_t>(c, smi);
+    if (threadIdx.x == 0) tile_cnt[t] = c;
+  }
+  if (!tail_gate(&ctrl->ctr_iso, nblk_)) return;
+  int32_t carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    const int32_t x = t < ntiles ? tile_cnt[t] : 0;
+    int32_t tot;
+    const int32_t ex = block_exscan<kBlock, int32_t>(x, smi, &tot);
+    if (t < ntiles) tile_cnt[t] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctrl->niso = carry;
+}
+
+__device__ __forceinline__ void b_iso_list(LevelView lv, const int32_t* match,
+                                                     const int32_t* tile_base, int32_t* iso,
+                                                     int ntiles, int bid_, int nblk_) {
+  __shared__ int32_t smi[kBlock / 64];
+  for (int t = bid_; t < ntiles; t += nblk_) {
+    const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
+    bool f[4];
+    int32_t c = 0;
+    for (int j = 0; j < 4; j++) {
+      const int64_t u = base + j;
+      f[j] = u < lv.n && match[u] == -1 && lv.xadj[u + 1] == lv.xadj[u];
+      c += f[j];
+    }
+    int32_t tot;
+    int32_t r = tile_base[t] + block_exscan<kBlock, int32_t>(c, smi, &tot);
+    for (int j = 0; j < 4; j++)
+      if (f[j]) iso[r++] = (int32_t)(base + j);
+  }
+}
+
+__device__ __forceinline__ void b_iso_pair(const int64_t* b, const int32_t* iso,
+                                                     int32_t* match, const Ctrl* ctrl, int bid_, int nblk_) {
+  const int32_t npairs = ctrl->niso / 2;
+  const int64_t cap = ctrl->cap;
+  for (int64_t i = (int64_t)bid_ * kBlock + threadIdx.x; i < npairs;
+       i += (int64_t)nblk_ * kBlock) {
+    const int32_t x = iso[2 * i], y = iso[2 * i + 1];
+    if (b[x] + b[y] <= cap) {
+      match[x] = y;
+      match[y] = x;
+    }
+  }
+}
+
+// --------------------------------------------------------------- contraction
+// tile t covers fine vertices [t*kTileV, (t+1)*kTileV); each thread 4 of them
+__device__ __forceinline__ void b_contract_count(LevelView lv, const int32_t* match,
+                                                           Ctrl* ctrl, int32_t* tile_lead,
+                                                           int64_t* tile_ub, int ntiles, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  __shared__ int32_t smi[kBlock / 64];
+  int64_t mx = 0;
+  for (int t = bid_; t < ntiles; t += nblk_) {
+    int32_t lead = 0;
+    int64_t ub = 0;
+    const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
+    for (int j = 0; j < 4; j++) {
+      const int64_t u = base + j;
+      if (u >= lv.n) break;
+      const int32_t m = match[u];
+      if (m < 0 || u < m) {
+        lead++;
+        ub += lv.xadj[u + 1] - lv.xadj[u];
+        int64_t bsum = lv.b[u];
+        if (m >= 0) {
+          ub += lv.xadj[m + 1] - lv.xadj[m];
+          bsum += lv.b[m];
+        }
+        mx = bsum > mx ? bsum : mx;
+      }
+    }
+    lead = block_sum<kBlock, int32_t>(lead, smi);
+    ub = block_sum<kBlock, int64_t>(ub, sml);
+    if (threadIdx.x == 0) {
+      tile_lead[t] = lead;
+      tile_ub[t] = ub;
+    }
+  }
+  mx = block_max<kBlock, int64_t>(mx, sml);
+  if (threadIdx.x == 0) atomicMax((long long*)&ctrl->maxb_next, (long long)mx);
+  if (!tail_gate(&ctrl->ctr_count, nblk_)) return;
+  // exclusive scan of the tile totals
+  int32_t carry_l = 0;
+  int64_t carry_u = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    int32_t l = t < ntiles ? tile_lead[t] : 0;
+    int64_t u = t < ntiles ? tile_ub[t] : 0;
+    int32_t tl;
+    int64_t tu;
+    int32_t el = block_exscan<kBlock, int32_t>(l, smi, &tl);
+    int64_t eu = block_exscan<kBlock, int64_t>(u, sml, &tu);
+    if (t < ntiles) {
+      tile_lead[t] = carry_l + el;
+      tile_ub[t] = carry_u + eu;
+    }
+    carry_l += tl;
+    carry_u += tu;
+  }
+  if (threadIdx.x == 0) {
+    ctrl->nc = carry_l;
+    ctrl->ubtot = carry_u;
+  }
+}
+
+__device__ __forceinline__ void b_contract_map(LevelView lv, const int32_t* match,
+                                                         const int64_t* vc, const int64_t* vg,
+                                                         const int32_t* tile_lead,
+                                                         const int64_t* tile_ub, int32_t* cmap,
+                                                         int64_t* cvc, int64_t* cvg,
+                                                         int32_t* cmem0, int32_t* cmem1,
+                                                         int64_t* toff, int ntiles, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  __shared__ int32_t smi[kBlock / 64];
+  for (int t = bid_; t < ntiles; t += nblk_) {
+    const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
+    int32_t lead = 0;
+    int64_t ub = 0;
+    int32_t mm[4];
+    for (int j = 0; j < 4; j++) {
+      const int64_t u = base + j;
+      mm[j] = -2;
+      if (u >= lv.n) continue;
+      const int32_t m = match[u];
+      mm[j] = m;
+      if (m < 0 || u < m) {
+        lead++;
+        ub += lv.xadj[u + 1] - lv.xadj[u];
+        if (m >= 0) ub += lv.xadj[m + 1] - lv.xadj[m];
+      }
+    }
+    int32_t tl;
+    int64_t tu;
+    int32_t c = tile_lead[t] + block_exscan<kBlock, int32_t>(lead, smi, &tl);
+    int64_t off = tile_ub[t] + block_exscan<kBlock, int64_t>(ub, sml, &tu);
+    for (int j = 0; j < 4; j++) {
+      const int64_t u = base + j;
+      const int32_t m = mm[j];
+      if (m == -2 || !(m < 0 || u < m)) continue;
+      cmap[u] = c;
+      int64_t sc = vc[u], sg = vg[u];
+      int64_t d = lv.xadj[u + 1] - lv.xadj[u];
+      if (m >= 0) {
+        cmap[m] = c;
+        sc += vc[m];
+        sg += vg[m];
+        d += lv.xadj[m + 1] - lv.xadj[m];
+      }
+      cvc[c] = sc;
+      cvg[c] = sg;
+      cmem0[c] = (int32_t)u;
+      cmem1[c] = m;
+      toff[c] = off;
+      c++;
+      off += d;
+    }
+  }
+}
+
+// candidate i of coarse row c: entries of the first member, then the second
+struct CoarseRowLoader {
+  const int32_t* xadj;
+  const int32_t* adj;
+  const int64_t* w;
+  const int32_t* cmap;
+  int32_t c, e0, d0, e1;
+  __device__ __forceinline__ void operator()(int i, int32_t& k, int64_t& v) const {
+    const int32_t e = i < d0 ? e0 + i : e1 + (i - d0);
+    const int32_t x = cmap[adj[e]];
+    k = x == c ? INT_MAX : x;
+    v = w[e];
+  }
+};
+
+__device__ __forceinline__ CoarseRowLoader coarse_loader(const LevelView& lv, const int32_t* cmap,
+                                                         const int32_t* cmem0,
+                                                         const int32_t* cmem1, int32_t c,
+                                                         int* L) {
+  CoarseRowLoader ld;
+  ld.xadj = lv.xadj;
+  ld.adj = lv.adj;
+  ld.w = lv.w;
+  ld.cmap = cmap;
+  ld.c = c;
+  const int32_t m0 = cmem0[c], m1 = cmem1[c];
+  ld.e0 = lv.xadj[m0];
+  ld.d0 = lv.xadj[m0 + 1] - ld.e0;
+  ld.e1 = m1 >= 0 ? lv.xadj[m1] : 0;
+  const int d1 = m1 >= 0 ? lv.xadj[m1 + 1] - ld.e1 : 0;
+  *L = ld.d0 + d1;
+  return ld;
+}
+
+template <int T>
+__device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32_t* okey,
+                                         int64_t* oval, int32_t* cnt_out) {
+  const int lane = threadIdx.x & (T - 1);
+  int32_t k = INT_MAX;
+  int64_t v = 0;
+  if (lane < L) ld(lane, k, v);
+  team_bitonic<T>(k, v);
+  bool dummy = false;
+  int cnt = team_emit<T, true>(k, v, okey, oval, &dummy);
+  if (lane == 0) *cnt_out = cnt;
+}
+
+__device__ __forceinline__ void b_contract_rows(
+    LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
+    const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
+    int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, unsigned char* lds,
+    int bid_, int nblk_) {
+  // lds: kRowBlockCap x (int64 + int32) bytes, split into kBlock/64 wave-private
+  // regions of kWaveCap entries for the wave sorts
+  int64_t* sv = (int64_t*)lds;
+  int32_t* sk = (int32_t*)(sv + kRowBlockCap);
+  __shared__ int32_t smi[kBlock / 64];
+  __shared__ int64_t sml[kBlock / 64];
+  static_assert(kWaveCap * (kBlock / 64) <= kRowBlockCap, "wave regions exceed the block region");
+  const int32_t nc = ctrl->nc;
+  const int wave = threadIdx.x / 64;
+  for (int t = bid_; t < ntiles_c; t += nblk_) {
+    const int32_t c0 = t * kTileC;
+    const int32_t c1 = c0 + kTileC < nc ? c0 + kTileC : nc;
+    // rows of at most 16 candidates: 16-lane teams
+    for (int32_t c = c0 + (int32_t)threadIdx.x / 16; c < c1; c += kBlock / 16) {
+      int L;
+      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
+      if (L <= 16) team_row<16>(ld, L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+    }
+    // 17..64 candidates: one wave in registers; 65..kWaveCap: one wave in LDS
+    for (int32_t c = c0 + wave; c < c1; c += kBlock / 64) {
+      int L;
+      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
+      if (L > 16 && L <= 64) {
+        team_row<64>(ld, L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+      } else if (L > 64 && L <= kWaveCap) {
+        bool dummy = false;
+        int k = wave_sort_emit<true>(L, ld, sk + wave * kWaveCap, sv + wave * kWaveCap,
+                                     tmpk + toff[c], tmpv + toff[c], &dummy);
+        if (lane_id() == 0) cnt[c] = k;
+      }
+    }
+    __syncthreads();
+    // longer rows: the whole block in LDS, or deferred to the dense merge
+    for (int32_t c = c0; c < c1; c++) {
+      int L;
+      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
+      if (L <= kWaveCap) continue;
+      if (L <= kRowBlockCap) {
+        bool dummy = false;
+        int k = block_sort_emit<kBlock, true>(L, ld, sk, sv, tmpk + toff[c], tmpv + toff[c],
+                                              &dummy, smi);
+        if (threadIdx.x == 0) cnt[c] = k;
+      } else if (threadIdx.x == 0) {
+        int slot = atomicAdd(&wctrl->nlong, 1);
+        longlist[slot] = c;
+        cnt[c] = 0;
+      }
+    }
+    __syncthreads();
+    int64_t s = 0;
+    for (int32_t c = c0 + threadIdx.x; c < c1; c += kBlock) s += cnt[c];
+    s = block_sum<kBlock, int64_t>(s, sml);
+    if (threadIdx.x == 0) tile_cnt[t] = s;
+  }
+}
+
+__device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cmap,
+                                                          const int32_t* cmem0,
+                                                          const int32_t* cmem1,
+                                                          const int64_t* toff, Ctrl* ctrl,
+                                                          int32_t* tmpk, int64_t* tmpv,
+                                                          int32_t* cnt, int64_t* tile_cnt,
+                                                          const int32_t* longlist,
+                                                          int ntiles_c, unsigned char* lds, int bid_, int nblk_) {
+  // lds: kWin x (int64 + int32) bytes
+  int64_t* acc = (int64_t*)lds;
+  int32_t* cc = (int32_t*)(acc + kWin);
+  __shared__ int32_t smi[kBlock / 64];
+  __shared__ int64_t sml[kBlock / 64];
+  const int32_t nlong = ctrl->nlong;
+  for (int32_t i = bid_; i < nlong; i += nblk_) {
+    const int32_t c = longlist[i];
+    int L;
+    CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
+    bool dummy = false;
+    int k = block_dense_emit<kBlock, true>(L, ld, acc, cc, smi, sml, tmpk + toff[c],
+                                           tmpv + toff[c], &dummy);
+    if (threadIdx.x == 0) {
+      cnt[c] = k;
+      atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
+    }
+  }
+  if (!tail_gate(&ctrl->ctr_long, nblk_)) return;
+  int64_t carry = 0;
+  for (int t0 = 0; t0 < ntiles_c; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    int64_t x = t < ntiles_c ? tile_cnt[t] : 0;
+    int64_t tot;
+    int64_t e = block_exscan<kBlock, int64_t>(x, sml, &tot);
+    if (t < ntiles_c) tile_cnt[t] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctrl->nnz_c = (int32_t)carry;
+}
+
+__device__ __forceinline__ void b_contract_compact(const Ctrl* ctrl,
+                                                             const int64_t* toff,
+                                                             const int32_t* cnt,
+                                                             const int64_t* tile_base,
+                                                             const int32_t* tmpk,
+                                                             const int64_t* tmpv, int32_t* cxadj,
+                                                             int32_t* cadj, int64_t* cw,
+                                                             int ntiles_c, int bid_, int nblk_) {
+  __shared__ int32_t smi[kBlock / 64];
+  __shared__ int32_t srow[kTileC + 1];
+  const int32_t nc = ctrl->nc;
+  for (int t = bid_; t < ntiles_c; t += nblk_) {
+    const int32_t c0 = t * kTileC;
+    const int32_t c = c0 + threadIdx.x;
+    const int32_t k = (c < nc && threadIdx.x < kTileC) ? cnt[c] : 0;
+    int32_t tot;
+    const int32_t ex = block_exscan<kBlock, int32_t>(k, smi, &tot);
+    const int64_t base = tile_base[t];
+    if (c < nc && threadIdx.x < kTileC) {
+      cxadj[c] = (int32_t)(base + ex);
+      srow[threadIdx.x] = ex;
+    }
+    if (c == nc - 1) cxadj[nc] = (int32_t)(base + ex + k);
+    __syncthreads();
+    const int32_t rows = (c0 + kTileC < nc ? kTileC : nc - c0);
+    // copy: 16-lane teams over rows
+    for (int r = threadIdx.x / 16; r < rows; r += kBlock / 16) {
+      const int32_t cr = c0 + r;
+      const int32_t kr = cnt[cr];
+      const int64_t src = toff[cr];
+      const int64_t dst = base + srow[r];
+      for (int j = threadIdx.x & 15; j < kr; j += 16) {
+        cadj[dst + j] = tmpk[src + j];
+        cw[dst + j] = tmpv[src + j];
+      }
+    }
+    __syncthreads();
+  }
+  if (nc == 0 && bid_ == 0 && threadIdx.x == 0) cxadj[0] = 0;
+}
+
+// ------------------------------------------------------------------ refinement
+__device__ __forceinline__ void plan_pass(const RefCtl& r, int* mode, int* s) {
+  if (r.pw[0] > r.maxw[0]) {
+    *mode = 1;
+    *s = 0;
+  } else if (r.pw[1] > r.maxw[1]) {
+    *mode = 1;
+    *s = 1;
+  } else {
+    *mode = 0;
+    *s = r.pass & 1;
+  }
+}
+
+__device__ __forceinline__ void clear_pass_acc(RefCtl* rc) {
+  rc->ext_sum = 0;
+  rc->cand_b = 0;
+  rc->gmin_acc = INT64_MAX;
+  rc->gmax_acc = INT64_MIN;
+  rc->ncand = 0;
+  rc->moved_b = 0;
+  rc->moved_n = 0;
+}
+
+// Called by every thread of one block once the pass totals are known.
+template <int BS, class Items>
+__device__ void decide_admission(RefCtl* rc, const Items& items, uint32_t ncand, int64_t cand_b,
+                                 int64_t gmin, int64_t gmax, int32_t n, SelShared* sh) {
+  const int mode = rc->mode, s = rc->s, d = 1 - s;
+  const int64_t budget = rc->maxw[d] - rc->pw[d];
+  int admit;
+  u128 thr = 0;
+  int idbits = bitlen64((uint64_t)(n > 0 ? n - 1 : 0));
+  if (ncand == 0) {
+    admit = kAdmitNone;
+  } else if (mode == 0 && cand_b <= budget) {
+    admit = kAdmitAll;
+  } else {
+    const int tbits = bitlen64((uint64_t)(gmax - gmin)) + idbits;
+    if (mode == 0) {
+      thr = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh);
+    } else {
+      const int64_t excess = rc->pw[s] - rc->maxw[s];
+      u128 t1 = select_prefix<BS>(items, gmin, idbits, tbits, 1, excess, sh);
+      u128 t2 = 0;
+      if (cand_b > budget) t2 = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh);
+      thr = t1 > t2 ? t1 : t2;
+    }
+    admit = kAdmitThr;
+  }
+  if (threadIdx.x == 0) {
+    rc->admit = admit;
+    rc->idbits = idbits;
+    rc->gmin = gmin;
+    rc->thr_hi = (uint64_t)(thr >> 64);
+    rc->thr_lo = (uint64_t)thr;
+  }
+}
+
+__device__ __forceinline__ bool admitted(const RefCtl& r, const Cand& c) {
+  if (r.admit == kAdmitAll) return true;
+  if (r.admit == kAdmitNone) return false;
+  const u128 thr = ((u128)r.thr_hi << 64) | (u128)r.thr_lo;
+  return cand_key(c, r.gmin, r.idbits) >= thr;
+}
+
+__device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_b, int64_t moved_n) {
+  const int s = rc->s, d = 1 - s;
+  rc->pw[s] -= moved_b;
+  rc->pw[d] += moved_b;
+  rc->total_moves += moved_n;
+  rc->last_cut = rc->ext_sum / 2;
+  if (rc->mode == 1) rc->z = 0;
+  else rc->z = moved_n == 0 ? rc->z + 1 : 0;
+  rc->pass++;
+  rc->done = (rc->z >= 2 || rc->pass >= rc->npass) ? 1 : 0;
+  clear_pass_acc(rc);
+}
+
+template <int TW>
+__device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
+                                                        RefCtl* rc, Cand* list, SelShared* sel,
+                                                        int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  if (rc->done) return;
+  int mode, s;
+  plan_pass(*rc, &mode, &s);
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+  // every team runs the same number of iterations so that the wave-wide
+  // candidate ballot sees all of its lanes
+  const int64_t iters = (lv.n + nteams - 1) / nteams;
+  for (int64_t it = 0; it < iters; it++) {
+    const int64_t uu = team + it * nteams;
+    bool cand = false;
+    Cand c;
+    c.pad = 0;
+    if (uu < lv.n) {
+      const int32_t v = (int32_t)uu;
+      const int8_t pv = part[v];
+      int64_t ext = 0, in = 0;
+      const int32_t e1 = lv.xadj[v + 1];
+      for (int32_t e = lv.xadj[v] + lane; e < e1; e += TW) {
+        const int64_t w = lv.w[e];
+        if (part[lv.adj[e]] != pv) ext += w;
+        else in += w;
+      }
+      ext = team_sum<TW>(ext);
+      in = team_sum<TW>(in);
+      if (lane == 0) {
+        const int64_t gain = ext - in;
+        ext_acc += ext;
+        cand = pv == s && (mode == 1 || gain > 0);
+        if (cand) {
+          c.gain = gain;
+          c.b = lv.b[v];
+          c.v = v;
+          cb += c.b;
+          gmn = gain < gmn ? gain : gmn;
+          gmx = gain > gmx ? gain : gmx;
+        }
+      }
+    }
+    append_cand(cand, c, list, &rc->ncand);
+  }
+  ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+  cb = block_sum<kBlock, int64_t>(cb, sml);
+  gmn = block_min<kBlock, int64_t>(gmn, sml);
+  gmx = block_max<kBlock, int64_t>(gmx, sml);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&rc->ext_sum, (unsigned long long)ext_acc);
+    atomicAdd((unsigned long long*)&rc->cand_b, (unsigned long long)cb);
+    atomicMin((long long*)&rc->gmin_acc, (long long)gmn);
+    atomicMax((long long*)&rc->gmax_acc, (long long)gmx);
+  }
+  if (!tail_gate(&rc->ctr_gain, nblk_)) return;
+  if (threadIdx.x == 0) {
+    rc->mode = mode;
+    rc->s = s;
+  }
+  __syncthreads();
+  const ListItems items{list, rc->ncand};
+  decide_admission<kBlock>(rc, items, rc->ncand, rc->cand_b, rc->gmin_acc, rc->gmax_acc, lv.n,
+                           sel);
+}
+
+__device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
+                                                         const Cand* list, int32_t* pass_out, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  if (rc->done) return;
+  const RefCtl r = *rc;
+  const int d = 1 - r.s;
+  int64_t mb = 0, mn = 0;
+  for (int64_t i = (int64_t)bid_ * kBlock + threadIdx.x; i < r.ncand;
+       i += (int64_t)nblk_ * kBlock) {
+    const Cand c = list[i];
+    if (admitted(r, c)) {
+      part[c.v] = (int8_t)d;
+      mb += c.b;
+      mn++;
+    }
+  }
+  mb = block_sum<kBlock, int64_t>(mb, sml);
+  mn = block_sum<kBlock, int64_t>(mn, sml);
+  if (threadIdx.x == 0 && (mb || mn)) {
+    atomicAdd((unsigned long long*)&rc->moved_b, (unsigned long long)mb);
+    atomicAdd((unsigned long long*)&rc->moved_n, (unsigned long long)mn);
+  }
+  if (!tail_gate(&rc->ctr_apply, nblk_)) return;
+  if (threadIdx.x == 0) {
+    finish_pass(rc, rc->moved_b, rc->moved_n);
+    *pass_out = rc->pass;
+  }
+}
+
+__device__ __forceinline__ void start_level(RefCtl* rc, int npass) {
+  rc->pass = 0;
+  rc->z = 0;
+  rc->npass = npass;
+  rc->done = npass <= 0 ? 1 : 0;
+  rc->total_moves = 0;
+  clear_pass_acc(rc);
+}
+
+__device__ __forceinline__ void b_project(int32_t n, const int32_t* cmap,
+                                                    const int8_t* cpart, int8_t* part, RefCtl* rc,
+                                                    int npass, int bid_, int nblk_) {
+  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
+       u += (int64_t)nblk_ * kBlock)
+    part[u] = cpart[cmap[u]];
+  if (bid_ == 0 && threadIdx.x == 0) start_level(rc, npass);
+}
+
+__device__ __forceinline__ void b_start_level(RefCtl* rc, int npass, int bid_, int nblk_) {
+  if (threadIdx.x == 0) start_level(rc, npass);
+}
+
+// cut (as sum of ext), loads and times of the final assignment
+template <int TW>
+__device__ __forceinline__ void b_final_stats(LevelView lv, const int64_t* vc,
+                                                        const int64_t* vg, const int8_t* part,
+                                                        Ctrl* ctrl, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  int64_t ext_acc = 0, l0 = 0, l1 = 0, t0 = 0, t1 = 0;
+  for (int64_t uu = team; uu < lv.n; uu += nteams) {
+    const int32_t v = (int32_t)uu;
+    const int8_t pv = part[v];
+    int64_t ext = 0;
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW)
+      if (part[lv.adj[e]] != pv) ext += lv.w[e];
+    ext = team_sum<TW>(ext);
+    if (lane == 0) {
+      ext_acc += ext;
+      if (pv == 0) {
+        l0 += lv.b[v];
+        t0 += vc[v];
+      } else {
+        l1 += lv.b[v];
+        t1 += vg[v];
+      }
+    }
+  }
+  ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+  l0 = block_sum<kBlock, int64_t>(l0, sml);
+  l1 = block_sum<kBlock, int64_t>(l1, sml);
+  t0 = block_sum<kBlock, int64_t>(t0, sml);
+  t1 = block_sum<kBlock, int64_t>(t1, sml);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&ctrl->res_ext, (unsigned long long)ext_acc);
+    atomicAdd((unsigned long long*)&ctrl->res_load[0], (unsigned long long)l0);
+    atomicAdd((unsigned long long*)&ctrl->res_load[1], (unsigned long long)l1);
+    atomicAdd((unsigned long long*)&ctrl->res_time[0], (unsigned long long)t0);
+    atomicAdd((unsigned long long*)&ctrl->res_time[1], (unsigned long long)t1);
+  }
+}
+
+__device__ __forceinline__ void b_clear_stats(Ctrl* ctrl, int bid_, int nblk_) {
+  if (threadIdx.x == 0) {
+    ctrl->res_ext = 0;
+    ctrl->res_load[0] = ctrl->res_load[1] = 0;
+    ctrl->res_time[0] = ctrl->res_time[1] = 0;
+  }
+}
+
+// ------------------------------------------------------- initial bisection
+__device__ __forceinline__ void b_init_tot(LevelView lv, int64_t* tot, int bid_, int nblk_) {
+  for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < lv.n;
+       v += (int64_t)nblk_ * kBlock) {
+    int64_t s = 0;
+    for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) s += lv.w[e];
+    tot[v] = s;
+  }
+}
+
+// growing key: (has a neighbour in g, gain towards g, smaller id)
+struct GrowBest {
+  int32_t a;
+  int64_t g;
+  int32_t v;  // -1: none
+};
+
+__device__ __forceinline__ bool grow_better(const GrowBest& x, const GrowBest& y) {
+  if (y.v < 0) return x.v >= 0;
+  if (x.v < 0) return false;
+  if (x.a != y.a) return x.a > y.a;
+  if (x.g != y.g) return x.g > y.g;
+  return x.v < y.v;
+}
+
+template <int BS>
+__device__ GrowBest block_grow_argmax(GrowBest b, GrowBest* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    GrowBest o2;
+    o2.a = __shfl_xor(b.a, o, 64);
+    o2.g = __shfl_xor(b.g, o, 64);
+    o2.v = __shfl_xor(b.v, o, 64);
+    if (grow_better(o2, b)) b = o2;
+  }
+  if (BS == 64) return b;
+  if (lane_id() == 0) sm[threadIdx.x / 64] = b;
+  __syncthreads();
+  GrowBest r = sm[0];
+  for (int i = 1; i < BS / 64; i++)
+    if (grow_better(sm[i], r)) r = sm[i];
+  __syncthreads();
+  return r;
+}
+
+// Whole-graph refinement inside one block (coarsest level, per trial).
+template <int BS>
+__device__ void refine_block(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                             SelShared* sel, int64_t* sml, uint32_t* s_ncand) {
+  for (;;) {
+    __syncthreads();
+    if (rc->done) break;
+    int mode, s;
+    plan_pass(*rc, &mode, &s);
+    if (threadIdx.x == 0) *s_ncand = 0;
+    __syncthreads();
+    int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+    const int iters = (lv.n + BS - 1) / BS;
+    for (int it = 0; it < iters; it++) {
+      const int32_t v = it * BS + threadIdx.x;
+      bool cand = false;
+      Cand c;
+      c.pad = 0;
+      if (v < lv.n) {
+        const int8_t pv = part[v];
+        int64_t ext = 0, in = 0;
+        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
+          if (part[lv.adj[e]] != pv) ext += lv.w[e];
+          else in += lv.w[e];
+        }
+        const int64_t gain = ext - in;
+        ext_acc += ext;
+        cand = pv == s && (mode == 1 || gain > 0);
+        if (cand) {
+          c.gain = gain;
+          c.b = lv.b[v];
+          c.v = v;
+          cb += c.b;
+          gmn = gain < gmn ? gain : gmn;
+          gmx = gain > gmx ? gain : gmx;
+        }
+      }
+      append_cand(cand, c, list, s_ncand);
+    }
+    ext_acc = block_sum<BS, int64_t>(ext_acc, sml);
+    cb = block_sum<BS, int64_t>(cb, sml);
+    gmn = block_min<BS, int64_t>(gmn, sml);
+    gmx = block_max<BS, int64_t>(gmx, sml);
+    __threadfence_block();
+    __syncthreads();
+    const uint32_t ncand = *s_ncand;
+    if (threadIdx.x == 0) {
+      rc->mode = mode;
+      rc->s = s;
+      rc->ext_sum = ext_acc;
+    }
+    __syncthreads();
+    const ListItems items{list, ncand};
+    decide_admission<BS>(rc, items, ncand, cb, gmn, gmx, lv.n, sel);
+    __syncthreads();
+    const RefCtl r = *rc;
+    int64_t mb = 0, mn = 0;
+    for (uint32_t i = threadIdx.x; i < ncand; i += BS) {
+      const Cand c = list[i];
+      if (admitted(r, c)) {
+        part[c.v] = (int8_t)(1 - s);
+        mb += c.b;
+        mn++;
+      }
+    }
+    mb = block_sum<BS, int64_t>(mb, sml);
+    mn = block_sum<BS, int64_t>(mn, sml);
+    if (threadIdx.x == 0) finish_pass(rc, mb, mn);
+  }
+}
+
+// One block per trial: greedy growing, then refinement, then its cut.  The
+// last block to finish keeps the first trial minimal in (infeasible, cut).
+// keeps the first trial minimal in (infeasible, cut): its loads go to
+// ctrl->ref, its assignment to out_part
+template <int BS>
+__device__ void b_trial_pick(int K, int32_t n, Ctrl* ctrl, const RefCtl* tctl,
+                             const int8_t* tpart, const int64_t* tres, int8_t* out_part) {
+  __shared__ int s_best;
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int i = 1; i < K; i++) {
+      const int64_t ci = tres[2 * i], ii = tres[2 * i + 1];
+      const int64_t cbst = tres[2 * best], ib = tres[2 * best + 1];
+      if (ii < ib || (ii == ib && ci < cbst)) best = i;
+    }
+    s_best = best;
+    ctrl->ref.pw[0] = tctl[best].pw[0];
+    ctrl->ref.pw[1] = tctl[best].pw[1];
+    ctrl->ref.last_cut = tres[2 * best];
+  }
+  __syncthreads();
+  const int8_t* bp = tpart + (int64_t)s_best * n;
+  for (int32_t v = threadIdx.x; v < n; v += BS) out_part[v] = bp[v];
+  __syncthreads();
+}
+
+template <int BS>
+// Trial t of K with its state in global memory (coarsest graphs too large
+// for LDS); writes cut, infeasibility, loads and assignment of the trial.
+__device__ void b_trial_global(LevelView lv, const int64_t* tot, int K, int t, int gs, int npass,
+                               const Ctrl* ctrl, RefCtl* tctl, int8_t* tpart, int64_t* tconn,
+                               int32_t* tadj, Cand* tlist, int64_t* tres, SelShared* selp) {
+  __shared__ int64_t sml[BS / 64];
+  __shared__ GrowBest sgb[BS / 64];
+  __shared__ uint32_t s_ncand;
+  SelShared& sel = *selp;
+  const int32_t n = lv.n;
+  const int gb = 1 - gs;
+  int8_t* part = tpart + (int64_t)t * n;
+  int64_t* conn = tconn + (int64_t)t * n;
+  int32_t* adjc = tadj + (int64_t)t * n;
+  RefCtl* rc = tctl + t;
+  const int64_t tg = ctrl->tgt[gs], mg = ctrl->ref.maxw[gs];
+  int64_t W = 0;
+  for (int32_t v = threadIdx.x; v < n; v += BS) {
+    part[v] = (int8_t)gb;
+    conn[v] = 0;
+    adjc[v] = 0;
+    W += lv.b[v];
+  }
+  W = block_sum<BS, int64_t>(W, sml);
+  const int32_t seedv = (int32_t)(((int64_t)t * n) / K);
+  int64_t pg = 0;
+  bool first = true;
+  __syncthreads();
+  while (pg < tg) {
+    int32_t pick = -1;
+    if (first && pg + lv.b[seedv] <= mg) {
+      pick = seedv;
+    } else {
+      GrowBest best;
+      best.v = -1;
+      best.a = 0;
+      best.g = 0;
+      for (int32_t v = threadIdx.x; v < n; v += BS) {
+        if (part[v] != gb || pg + lv.b[v] > mg) continue;
+        GrowBest x;
+        x.a = adjc[v] > 0;
+        x.g = 2 * conn[v] - tot[v];
+        x.v = v;
+        if (grow_better(x, best)) best = x;
+      }
+      best = block_grow_argmax<BS>(best, sgb);
+      pick = best.v;
+    }
+    first = false;
+    if (pick < 0) break;
+    if (threadIdx.x == 0) part[pick] = (int8_t)gs;
+    for (int32_t e = lv.xadj[pick] + threadIdx.x; e < lv.xadj[pick + 1]; e += BS) {
+      const int32_t x = lv.adj[e];
+      conn[x] += lv.w[e];
+      adjc[x] += 1;
+    }
+    pg += lv.b[pick];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    rc->maxw[0] = ctrl->ref.maxw[0];
+    rc->maxw[1] = ctrl->ref.maxw[1];
+    rc->pw[gs] = pg;
+    rc->pw[gb] = W - pg;
+    start_level(rc, npass);
+  }
+  __syncthreads();
+  refine_block<BS>(lv, part, rc, tlist + (int64_t)t * (n > 0 ? n : 1), &sel, sml, &s_ncand);
+  __syncthreads();
+  int64_t ext = 0;
+  for (int32_t v = threadIdx.x; v < n; v += BS) {
+    const int8_t pv = part[v];
+    for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++)
+      if (part[lv.adj[e]] != pv) ext += lv.w[e];
+  }
+  ext = block_sum<BS, int64_t>(ext, sml);
+  if (threadIdx.x == 0) {
+    tres[2 * t] = ext / 2;
+    tres[2 * t + 1] = (rc->pw[0] > rc->maxw[0] || rc->pw[1] > rc->maxw[1]) ? 1 : 0;
+  }
+  __syncthreads();
+}
+
+// LDS-resident trials (coarsest graphs of at most kTrialLdsMax vertices):
+// one block of BS threads per trial.  Gains are kept up to date instead of
+// recomputed: when a set M of vertices changes side (all from one side to
+// the other), gain(x) flips sign for x in M, and every neighbour y of a moved
+// vertex gains -2w when it ends on the mover's new side, +2w otherwise.  This
+// yields the same integers as recomputing ext - int from scratch.
+constexpr int kTrialBlock = 256;
+constexpr int kTrialLdsMax = 3072;
+
+__device__ __forceinline__ size_t trial_lds_bytes(int32_t n) { return (size_t)n * 19 + 16; }
+
+// Trial t of K on an LDS-resident copy of the coarsest graph; writes its
+// cut, infeasibility, loads and assignment to tres / tctl / tpart.
+// lds: trial_lds_bytes(n) bytes; sel, srf: block-shared scratch.
+template <int BS>
+__device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int gs, int npass,
+                            const Ctrl* ctrl, RefCtl* tctl, int8_t* tpart, int64_t* tres,
+                            unsigned char* lds, SelShared* selp, RefCtl* srfp) {
+  const int32_t n = lv.n;
+  int64_t* s_gain = (int64_t*)lds;
+  int64_t* s_b = s_gain + n;
+  int8_t* s_part = (int8_t*)(s_b + n);
+  int8_t* s_adj = s_part + n;
+  int8_t* s_mv = s_adj + n;
+  __shared__ int64_t sml[BS / 64];
+  __shared__ GrowBest sgb[BS / 64];
+  SelShared& sel = *selp;
+  RefCtl& srf = *srfp;
+  const int gb = 1 - gs;
+  int64_t W = 0;
+  for (int32_t v = threadIdx.x; v < n; v += BS) {
+    s_gain[v] = -tot[v];
+    const int64_t bv = lv.b[v];
+    s_b[v] = bv;
+    s_part[v] = (int8_t)gb;
+    s_adj[v] = 0;
+    s_mv[v] = 0;
+    W += bv;
+  }
+  W = block_sum<BS, int64_t>(W, sml);
+  const int64_t tg = ctrl->tgt[gs], mg = ctrl->ref.maxw[gs];
+  const int32_t seedv = (int32_t)(((int64_t)t * n) / K);
+  int64_t pg = 0;
+  bool first = true;
+  // greedy growing of side gs, one vertex at a time
+  while (pg < tg) {
+    int32_t pick = -1;
+    if (first && pg + s_b[seedv] <= mg) {
+      pick = seedv;
+    } else {
+      GrowBest best;
+      best.v = -1;
+      best.a = 0;
+      best.g = 0;
+      for (int32_t v = threadIdx.x; v < n; v += BS) {
+        if (s_part[v] != gb || pg + s_b[v] > mg) continue;
+        GrowBest x;
+        x.a = s_adj[v];
+        x.g = s_gain[v];
+        x.v = v;
+        if (grow_better(x, best)) best = x;
+      }
+      best = block_grow_argmax<BS>(best, sgb);
+      pick = best.v;
+    }
+    first = false;
+    if (pick < 0) break;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_part[pick] = (int8_t)gs;
+      s_gain[pick] = -s_gain[pick];
+    }
+    __syncthreads();
+    for (int32_t e = lv.xadj[pick] + threadIdx.x; e < lv.xadj[pick + 1]; e += BS) {
+      const int32_t y = lv.adj[e];
+      const int64_t w = lv.w[e];
+      s_adj[y] = 1;
+      atomicAdd((unsigned long long*)&s_gain[y],
+                (unsigned long long)(s_part[y] == gs ? -2 * w : 2 * w));
+    }
+    pg += s_b[pick];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    srf.maxw[0] = ctrl->ref.maxw[0];
+    srf.maxw[1] = ctrl->ref.maxw[1];
+    srf.pw[gs] = pg;
+    srf.pw[gb] = W - pg;
+    start_level(&srf, npass);
+  }
+  __syncthreads();
+  // refinement passes on the LDS state
+  for (;;) {
+    if (srf.done) break;
+    int mode, s;
+    plan_pass(srf, &mode, &s);
+    const LdsItems items{s_gain, s_b, s_part, n, s, mode};
+    int64_t cb = 0, cnt = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      Cand c;
+      if (!items.get(v, c)) continue;
+      cb += c.b;
+      cnt++;
+      gmn = c.gain < gmn ? c.gain : gmn;
+      gmx = c.gain > gmx ? c.gain : gmx;
+    }
+    cb = block_sum<BS, int64_t>(cb, sml);
+    cnt = block_sum<BS, int64_t>(cnt, sml);
+    gmn = block_min<BS, int64_t>(gmn, sml);
+    gmx = block_max<BS, int64_t>(gmx, sml);
+    if (threadIdx.x == 0) {
+      srf.mode = mode;
+      srf.s = s;
+    }
+    __syncthreads();
+    decide_admission<BS>(&srf, items, (uint32_t)cnt, cb, gmn, gmx, n, &sel);
+    __syncthreads();
+    const int d = 1 - s;
+    int64_t mb = 0, mn = 0;
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      Cand c;
+      if (items.get(v, c) && admitted(srf, c)) {
+        s_mv[v] = 1;
+        mb += c.b;
+        mn++;
+      }
+    }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS)
+      if (s_mv[v]) {
+        s_part[v] = (int8_t)d;
+        s_gain[v] = -s_gain[v];
+      }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS)
+      if (s_mv[v]) {
+        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
+          const int32_t y = lv.adj[e];
+          const int64_t w = lv.w[e];
+          atomicAdd((unsigned long long*)&s_gain[y],
+                    (unsigned long long)(s_part[y] == d ? -2 * w : 2 * w));
+        }
+        s_mv[v] = 0;
+      }
+    mb = block_sum<BS, int64_t>(mb, sml);
+    mn = block_sum<BS, int64_t>(mn, sml);
+    if (threadIdx.x == 0) finish_pass(&srf, mb, mn);
+    __syncthreads();
+  }
+  // cut = sum over v of (gain + tot) / 4
+  int64_t q = 0;
+  for (int32_t v = threadIdx.x; v < n; v += BS) q += s_gain[v] + tot[v];
+  q = block_sum<BS, int64_t>(q, sml);
+  int8_t* part = tpart + (int64_t)t * n;
+  for (int32_t v = threadIdx.x; v < n; v += BS) part[v] = s_part[v];
+  if (threadIdx.x == 0) {
+    tres[2 * t] = q / 4;
+    tres[2 * t + 1] = (srf.pw[0] > srf.maxw[0] || srf.pw[1] > srf.maxw[1]) ? 1 : 0;
+    tctl[t].pw[0] = srf.pw[0];
+    tctl[t].pw[1] = srf.pw[1];
+  }
+  __syncthreads();
+}
+
+// -------------------------------------------------------------- gp_create
+__device__ __forceinline__ void b_val_xadj(int32_t n, const int32_t* xadj, Ctrl* ctrl, int bid_, int nblk_) {
+  for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < n;
+       v += (int64_t)nblk_ * kBlock) {
+    if ((v == 0 && xadj[0] != 0) || xadj[v + 1] < xadj[v]) atomicOr(&ctrl->verr, kVInval);
+  }
+}
+
+// saturating block sum of values <= 2^62 (a + b never exceeds 2^63)
+__device__ __forceinline__ uint64_t sat62(uint64_t a, uint64_t b) {
+  const uint64_t lim = 1ull << 62;
+  uint64_t s = a + b;
+  return s > lim ? lim : s;
+}
+
+template <int BS>
+__device__ uint64_t block_sum_sat(uint64_t v, uint64_t* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = sat62(v, __shfl_xor(v, o, 64));
+  if (lane_id() == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  uint64_t r = 0;
+  for (int i = 0; i < BS / 64; i++) r = sat62(r, sm[i]);
+  __syncthreads();
+  return r;
+}
+
+// ranges, self loops, sortedness, weight sums; one 16-lane team per row
+__device__ __forceinline__ void b_val_rows(int32_t n, const int32_t* xadj,
+                                                     const int32_t* adj, const int64_t* w,
+                                                     const int64_t* vc, const int64_t* vg,
+                                                     Ctrl* ctrl, int bid_, int nblk_) {
+  __shared__ uint64_t smu[kBlock / 64];
+  __shared__ int64_t sml[kBlock / 64];
+  const uint64_t lim = 1ull << 62;
+  uint32_t err = 0, unsorted = 0;
+  uint64_t sw = 0, sc = 0, sg = 0;
+  int64_t mc = 0, mg = 0;
+  const int lane = threadIdx.x & 15;
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / 16;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / 16;
+  for (int64_t uu = team; uu < n; uu += nteams) {
+    const int32_t u = (int32_t)uu;
+    for (int32_t e = xadj[u] + lane; e < xadj[u + 1]; e += 16) {
+      const int32_t v = adj[e];
+      const int64_t x = w[e];
+      if (v < 0 || v >= n || x < 0) err |= kVRange;
+      else if (v == u) err |= kVSelf;
+      if (e + 1 < xadj[u + 1] && adj[e + 1] <= v) unsorted = 1;
+      if (x >= 0) sw = sat62(sw, (uint64_t)x < lim ? (uint64_t)x : lim);
+    }
+    if (lane == 0) {
+      const int64_t a = vc[u], b = vg[u];
+      if (a < 0 || b < 0) err |= kVRange;
+      if (a >= 0) {
+        sc = sat62(sc, (uint64_t)a < lim ? (uint64_t)a : lim);
+        mc = a > mc ? a : mc;
+      }
+      if (b >= 0) {
+        sg = sat62(sg, (uint64_t)b < lim ? (uint64_t)b : lim);
+        mg = b > mg ? b : mg;
+      }
+    }
+  }
+  sw = block_sum_sat<kBlock>(sw, smu);
+  sc = block_sum_sat<kBlock>(sc, smu);
+  sg = block_sum_sat<kBlock>(sg, smu);
+  mc = block_max<kBlock, int64_t>(mc, sml);
+  mg = block_max<kBlock, int64_t>(mg, sml);
+  if (err) atomicOr(&ctrl->verr, err);
+  if (unsorted) atomicOr(&ctrl->vunsorted, 1u);
+  if (threadIdx.x == 0) {
+    // every addend is <= 2^62; the flag is raised before a sum could wrap
+    uint64_t o;
+    o = atomicAdd((unsigned long long*)&ctrl->vsum_w, (unsigned long long)sw);
+    if (o + sw >= lim) atomicOr(&ctrl->verr, kVOverflow);
+    o = atomicAdd((unsigned long long*)&ctrl->vsum_c, (unsigned long long)sc);
+    if (o + sc >= lim) atomicOr(&ctrl->verr, kVOverflow);
+    o = atomicAdd((unsigned long long*)&ctrl->vsum_g, (unsigned long long)sg);
+    if (o + sg >= lim) atomicOr(&ctrl->verr, kVOverflow);
+    atomicMax((long long*)&ctrl->vmax_c, (long long)mc);
+    atomicMax((long long*)&ctrl->vmax_g, (long long)mg);
+  }
+}
+
+// sort every row by neighbour (no merging), flag repeated neighbours
+struct PlainRowLoader {
+  const int32_t* adj;
+  const int64_t* w;
+  int32_t e0;
+  __device__ __forceinline__ void operator()(int i, int32_t& k, int64_t& v) const {
+    k = adj[e0 + i];
+    v = w[e0 + i];
+  }
+};
+
+__device__ __forceinline__ void b_sort_rows(int32_t n, const int32_t* xadj,
+                                                      const int32_t* adj, const int64_t* w,
+                                                      int32_t* oadj, int64_t* ow, Ctrl* ctrl,
+                                                      unsigned char* lds, int bid_, int nblk_) {
+  // lds: kSortCap x (int64 + int32) bytes
+  int64_t* sv = (int64_t*)lds;
+  int32_t* sk = (int32_t*)(sv + kSortCap);
+  __shared__ int32_t smi[kBlock / 64];
+  bool dup = false;
+  for (int64_t u0 = (int64_t)bid_ * kTileC; u0 < n; u0 += (int64_t)nblk_ * kTileC) {
+    const int64_t u1 = u0 + kTileC < n ? u0 + kTileC : n;
+    for (int64_t u = u0 + threadIdx.x / 16; u < u1; u += kBlock / 16) {
+      const int32_t e0 = xadj[u], L = xadj[u + 1] - e0;
+      if (L > 16) continue;
+      const int lane = threadIdx.x & 15;
+      int32_t k = INT_MAX;
+      int64_t v = 0;
+      if (lane < L) {
+        k = adj[e0 + lane];
+        v = w[e0 + lane];
+      }
+      team_bitonic<16>(k, v);
+      team_emit<16, false>(k, v, oadj + e0, ow + e0, &dup);
+    }
+    for (int64_t u = u0 + threadIdx.x / 64; u < u1; u += kBlock / 64) {
+      const int32_t e0 = xadj[u], L = xadj[u + 1] - e0;
+      if (L <= 16 || L > 64) continue;
+      const int lane = threadIdx.x & 63;
+      int32_t k = INT_MAX;
+      int64_t v = 0;
+      if (lane < L) {
+        k = adj[e0 + lane];
+        v = w[e0 + lane];
+      }
+      team_bitonic<64>(k, v);
+      team_emit<64, false>(k, v, oadj + e0, ow + e0, &dup);
+    }
+    for (int64_t u = u0; u < u1; u++) {
+      const int32_t e0 = xadj[u], L = xadj[u + 1] - e0;
+      if (L <= 64 || L > kSortCap) continue;
+      PlainRowLoader ld{adj, w, e0};
+      block_sort_emit<kBlock, false>(L, ld, sk, sv, oadj + e0, ow + e0, &dup, smi);
+    }
+  }
+  if (dup) atomicOr(&ctrl->verr, kVDup);
+}
+
+// rows longer than kSortCap: dense merge over id windows, one block per row
+__device__ __forceinline__ void b_sort_long(int32_t n, const int32_t* xadj,
+                                                      const int32_t* adj, const int64_t* w,
+                                                      int32_t* oadj, int64_t* ow, Ctrl* ctrl,
+                                                      unsigned char* lds, int bid_, int nblk_) {
+  int64_t* acc = (int64_t*)lds;
+  int32_t* cc = (int32_t*)(acc + kWin);
+  __shared__ int32_t smi[kBlock / 64];
+  __shared__ int64_t sml[kBlock / 64];
+  bool dup = false;
+  for (int64_t u = bid_; u < n; u += nblk_) {
+    const int32_t e0 = xadj[u], L = xadj[u + 1] - e0;
+    if (L <= kSortCap) continue;
+    PlainRowLoader ld{adj, w, e0};
+    block_dense_emit<kBlock, false>(L, ld, acc, cc, smi, sml, oadj + e0, ow + e0, &dup);
+  }
+  if (dup) atomicOr(&ctrl->verr, kVDup);
+}
+
+// every entry u->v must have v->u with the same weight (rows sorted)
+__device__ __forceinline__ void b_val_sym(int32_t n, const int32_t* xadj,
+                                                    const int32_t* adj, const int64_t* w,
+                                                    Ctrl* ctrl, int bid_, int nblk_) {
+  const int lane = threadIdx.x & 15;
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / 16;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / 16;
+  bool bad = false;
+  for (int64_t uu = team; uu < n; uu += nteams) {
+    const int32_t u = (int32_t)uu;
+    for (int32_t e = xadj[u] + lane; e < xadj[u + 1]; e += 16) {
+      const int32_t v = adj[e];
+      int32_t lo = xadj[v], hi = xadj[v + 1] - 1;
+      bool found = false;
+      while (lo <= hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        const int32_t x = adj[mid];
+        if (x == u) {
+          found = w[mid] == w[e];
+          break;
+        }
+        if (x < u) lo = mid + 1;
+        else hi = mid - 1;
+      }
+      if (!found) bad = true;
+    }
+  }
+  if (bad) atomicOr(&ctrl->verr, kVAsym);
+}
+
+__device__ __forceinline__ void b_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_t* vg, int bid_, int nblk_) {
+  for (int64_t v = (int64_t)bid_ * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)nblk_ * blockDim.x) {
+    vc[v] = vwgt[2 * v];
+    vg[v] = vwgt[2 * v + 1];
+  }
+}
+
+
+}  // namespace gpk

@@ -1,0 +1,154 @@
+"""Batched persistent-kernel path vs the CPU oracle, graph by graph.
+
+Each graph's result from gp_partition_batch must equal the oracle's result
+for that graph alone (and so the single-graph path's), whatever the queue
+order, chunking or number of workgroups.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import dagen
+import oracle
+from helpers import complete_graph, edgeless_graph, path_graph, random_graph
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_graphs(seed: int, count: int):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        k = i % 6
+        if k == 0:
+            g = random_graph(int(rng.integers(1, 300)), float(rng.uniform(0.01, 0.2)), rng,
+                             wmax=int(rng.choice([1, 9, 1000])), vmax=9, const_w=bool(i % 4 == 0))
+        elif k == 1:
+            g = dagen.cholesky(int(rng.integers(2, 14)), 256, jitter_pm=100, seed=i)
+        elif k == 2:
+            g = dagen.layered(int(rng.integers(100, 6000)), int(rng.integers(2, 20)), rate=4,
+                              seed=i)
+        elif k == 3:
+            g = dagen.lu(int(rng.integers(2, 12)), 256, jitter_pm=50, seed=i)
+        elif k == 4:
+            g = path_graph(int(rng.integers(1, 500)))
+        else:
+            m = int(rng.integers(0, 40))
+            g = edgeless_graph(m, rng.integers(1, 5, m))
+        out.append(g)
+    return out
+
+
+def run_batch(gp, graphs, opts_kw, config=None):
+    import torch
+    b = dagen.concat(graphs)
+    dev = gp.batch_to_device(b)
+    bt = gp.Batch()
+    if config:
+        bt.config(*config)
+    part, res = bt.partition(*dev, opts=gp.options(**opts_kw))
+    torch.cuda.synchronize()
+    got = part.cpu().numpy()
+    bt.close()
+    return b, got, res
+
+
+def check_against_oracle(b, graphs, got, res, opts_kw, which=None):
+    oo = oracle.Options(**opts_kw)
+    idx = range(len(graphs)) if which is None else which
+    for g in idx:
+        gr = graphs[g]
+        ref = oracle.partition(gr, oo)
+        r = res[g]
+        assert r.status == ref.status, f"graph {g}: status {r.status} vs {ref.status}"
+        if ref.status != 0:
+            continue
+        p = got[b.voff[g]:b.voff[g + 1]]
+        assert np.array_equal(p, ref.part), f"graph {g} ({gr.name}, n={gr.n}): assignment differs"
+        assert r.cut == ref.cut and (r.load[0], r.load[1]) == ref.load, f"graph {g}"
+        assert (r.time[0], r.time[1]) == ref.time and r.feasible == ref.feasible, f"graph {g}"
+        assert r.levels == ref.levels, f"graph {g}"
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(coarsen_to=16, ratio=(1, 1)),
+                                dict(coarsen_to=64, balance_on=1, ratio=(2, 5), eps_ppm=0,
+                                     match_rounds=2, refine_passes=3, init_trials=5)],
+                         ids=["default", "deep", "odd"])
+def test_batch_mixed_matches_oracle(gp, kw):
+    graphs = mixed_graphs(11, 48)
+    say(f"case batch mixed {kw}")
+    b, got, res = run_batch(gp, graphs, kw)
+    check_against_oracle(b, graphs, got, res, kw)
+
+
+def test_batch_config_independent(gp):
+    graphs = mixed_graphs(5, 40)
+    kw = dict(coarsen_to=32)
+    say("case batch config A")
+    b, got1, res1 = run_batch(gp, graphs, kw)
+    say("case batch config B")
+    _, got2, res2 = run_batch(gp, graphs, kw, config=(7, 3, 1))
+    say("case batch config C")
+    _, got3, res3 = run_batch(gp, graphs, kw, config=(1, 64, 0))
+    assert np.array_equal(got1, got2) and np.array_equal(got1, got3)
+    for a, c, d in zip(res1, res2, res3):
+        assert a.as_dict() == c.as_dict() == d.as_dict()
+
+
+def test_batch_errors_per_graph(gp):
+    good = path_graph(30)
+    bad = path_graph(5)
+    bad.adjncy = bad.adjncy.copy()
+    bad.adjncy[1] = 1   # self loop in row 1
+    asym = path_graph(6)
+    asym.adjwgt = asym.adjwgt.copy()
+    asym.adjwgt[0] = 7
+    graphs = [good, bad, asym, complete_graph(12)]
+    say("case batch errors")
+    b, got, res = run_batch(gp, graphs, {})
+    assert [r.status for r in res] == [0, oracle.ESELF, oracle.EASYM, 0]
+    check_against_oracle(b, graphs, got, res, {}, which=[0, 3])
+
+
+def test_batch_uneven_sizes(gp):
+    # log-uniform sizes from the batch recipe, a reduced count
+    size, kind, param, gseed = dagen.batch_plan(96, 100, 50000, 7)
+    graphs = []
+    for i in range(96):
+        if kind[i] == 0:
+            graphs.append(dagen.cholesky(int(param[i]), 512, 0, 4, dagen.TILE_512_BYTES,
+                                         int(gseed[i])))
+        else:
+            graphs.append(dagen.layered(int(size[i]), int(param[i]), rate=4, seed=int(gseed[i])))
+    kw = dict(ratio=(1, 4), eps_ppm=30000)
+    say("case batch uneven 96")
+    b, got, res = run_batch(gp, graphs, kw)
+    check_against_oracle(b, graphs, got, res, kw)
+
+
+def test_batch_full_4096_sampled(gp):
+    """The 4,096-graph batch at full size (sizes 100..50,000, half Cholesky,
+    half layered), as the benchmark runs it; 40 sampled graphs against the
+    oracle and every graph against the single-graph GPU path's totals."""
+    graphs = dagen.batch(4096, 100, 50000, 0)
+    kw = dict(ratio=(1, 4), eps_ppm=30000)
+    say("case batch full 4096")
+    b, got, res = run_batch(gp, graphs, kw)
+    assert all(r.status == 0 for r in res)
+    rng = np.random.default_rng(0)
+    sample = sorted(set(rng.integers(0, 4096, 36).tolist()) | {0, 1, 4094, 4095})
+    check_against_oracle(b, graphs, got, res, kw, which=sample)
+    # the largest graphs through the single-graph path as well
+    sizes = np.diff(b.voff)
+    for g in np.argsort(-sizes)[:6].tolist():
+        h = gp.create(graphs[g])
+        p, r = h.partition(gp.options(**kw))
+        h.close()
+        assert np.array_equal(p.cpu().numpy(), got[b.voff[g]:b.voff[g + 1]])
+        assert r.cut == res[g].cut
