@@ -120,6 +120,20 @@ gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_
 
 void gp_destroy(gp_graph* g);
 
+/* Learned coarsest-level proposal (GP_LEARNED): a 3-layer message-passing
+ * network, hidden size 64, whose 25,153 BF16 parameters (uint16 bits, host
+ * memory) are laid out as Win[64][4], b_in[64], 3 x (Ws[64][64], Wn[64][64],
+ * b[64]), wo[64], bo (matrices [output][input]).  It scores the coarsest
+ * vertices; the best fill the grown side; refinement follows; the plain
+ * bisection is kept unless the learned one is strictly better in
+ * (infeasible, cut).  It runs when the coarsest graph has at most 3,072
+ * vertices.  *model is device state owned by the library. */
+gp_status gp_model_create(const uint16_t* params, int32_t count, const void** model);
+void gp_model_free(const void* model);
+/* The network's FP32 score of every vertex of g's graph (its canonical rows):
+ * scores is float[n], device memory unless g was created with GP_HOST_PTRS. */
+gp_status gp_model_scores(const void* model, gp_graph* g, float* scores);
+
 /* Per-kernel profile of the calls made while profiling is on (HIP events
  * around every launch; adds a host wait per level).  One row per kernel (and
  * team width): */
@@ -164,6 +178,39 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
                              const int64_t* vwgt, const gp_options* o, int8_t* part,
                              gp_result* res);
 void gp_batch_destroy(gp_batch* b);
+/* Export, during later gp_partition_batch calls, every graph's coarsest
+ * graph and its plain (greedy-growing + refinement) bisection - the training
+ * data of the learned proposal.  All pointers device memory.  rec: int64[4G]
+ * per graph = n, 2m, vertex slot, entry slot (-1 when the buffers are full);
+ * the graph's xadj (n+1 local offsets), vwgt (n x 2) and part (n) start at its
+ * vertex slot of xadj / vwgt / part (cap_vertices slots), its adjncy and
+ * adjwgt at its entry slot (cap_entries slots).  rec == NULL turns it off. */
+gp_status gp_batch_export(gp_batch* b, int64_t* rec, int32_t* xadj, int64_t* vwgt, int8_t* part,
+                          int64_t cap_vertices, int32_t* adjncy, int64_t* adjwgt,
+                          int64_t cap_entries);
+
+/* ---------------------------------------------------------------------
+ * Training of the learned proposal (GPU; MFMA BF16 -> FP32 dense layers,
+ * CSR message passing and its transpose, BCE-with-logits loss weighted by
+ * b_v / W_g and averaged over the graphs of a mini-batch, Adam on FP32
+ * master weights).  Not bit-exact; gradients are checked against an FP64
+ * reference within a tolerance.
+ * --------------------------------------------------------------------- */
+typedef struct gp_trainer gp_trainer;
+/* init_params: host float[25153] in the blob order of gp_model_create */
+gp_status gp_train_create(gp_trainer** t, const float* init_params, int32_t count, void* stream);
+/* The training set, device memory, in the batched layout (see
+ * gp_partition_batch); labels: int8 per vertex, 1 = on the grown side. */
+gp_status gp_train_set_data(gp_trainer* t, int32_t G, const int64_t* voff, const int64_t* eoff,
+                            const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
+                            const int64_t* vwgt, const int8_t* labels, int32_t balance_on);
+/* one Adam step on graphs [g0, g1); *loss (host, may be NULL) gets the batch loss */
+gp_status gp_train_step(gp_trainer* t, int32_t g0, int32_t g1, float lr, float* loss);
+/* the gradient (host float[25153]) and loss on graphs [g0, g1), no update */
+gp_status gp_train_grad(gp_trainer* t, int32_t g0, int32_t g1, float* grad, float* loss);
+/* FP32 master weights and/or their BF16 copy (host arrays, may be NULL) */
+gp_status gp_train_params(gp_trainer* t, float* f32, uint16_t* bf16);
+void gp_train_destroy(gp_trainer* t);
 
 const char* gp_strerror(gp_status s);
 

@@ -694,7 +694,8 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
     part = (int8_t*)malloc((size_t)(g->n > 0 ? g->n : 1));
     if (!part) rc = OR_ENOMEM;
     if (rc == OR_OK) rc = init_bisect_og(g, b, r0, r1, tgt, maxw, (int)K, (int)P, part, pw);
-    if (rc == OR_OK && (flags & OR_FLAG_LEARNED) && g->n > 0) {
+    /* the learned proposal runs on coarsest graphs of at most 3,072 vertices */
+    if (rc == OR_OK && (flags & OR_FLAG_LEARNED) && g->n > 0 && g->n <= 3072) {
       int8_t* lp = (int8_t*)malloc((size_t)g->n);
       int64_t lpw[2];
       int gs = r0 <= r1 ? 0 : 1;

@@ -90,6 +90,26 @@ def _load():
     lib.gp_partition_batch.restype = ctypes.c_int
     lib.gp_batch_destroy.argtypes = [vp]
     lib.gp_batch_destroy.restype = None
+    lib.gp_model_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.gp_model_create.restype = ctypes.c_int
+    lib.gp_model_free.argtypes = [vp]
+    lib.gp_model_free.restype = None
+    lib.gp_model_scores.argtypes = [vp, vp, vp]
+    lib.gp_model_scores.restype = ctypes.c_int
+    lib.gp_batch_export.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64]
+    lib.gp_batch_export.restype = ctypes.c_int
+    lib.gp_train_create.argtypes = [ctypes.POINTER(vp), vp, i32, vp]
+    lib.gp_train_create.restype = ctypes.c_int
+    lib.gp_train_set_data.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i32]
+    lib.gp_train_set_data.restype = ctypes.c_int
+    lib.gp_train_step.argtypes = [vp, i32, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
+    lib.gp_train_step.restype = ctypes.c_int
+    lib.gp_train_grad.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_float)]
+    lib.gp_train_grad.restype = ctypes.c_int
+    lib.gp_train_params.argtypes = [vp, vp, vp]
+    lib.gp_train_params.restype = ctypes.c_int
+    lib.gp_train_destroy.argtypes = [vp]
+    lib.gp_train_destroy.restype = None
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_strerror.restype = ctypes.c_char_p
     return lib
@@ -100,7 +120,9 @@ _lib = _load()
 EXPORTED = ["gp_options_default", "gp_ratio_from_times", "gp_create", "gp_set_stream",
             "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror",
             "gp_profile_enable", "gp_profile_read", "gp_batch_create", "gp_batch_config",
-            "gp_partition_batch", "gp_batch_destroy"]
+            "gp_partition_batch", "gp_batch_destroy", "gp_model_create", "gp_model_free",
+            "gp_model_scores", "gp_batch_export", "gp_train_create", "gp_train_set_data",
+            "gp_train_step", "gp_train_grad", "gp_train_params", "gp_train_destroy"]
 
 
 def strerror(status: int) -> str:
@@ -195,6 +217,18 @@ class Graph:
             return part, res, tr.reshape(trace_cap, 8)[:res.levels + 1].copy()
         return part, res
 
+    def scores(self, model: "Model"):
+        """The learned network's score of every vertex (float32[n])."""
+        import torch
+        if self.host:
+            out = np.zeros(max(self.n, 1), np.float32)
+        else:
+            out = torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device)
+        st = _lib.gp_model_scores(model.handle, self._h, _ptr(out))
+        if st != OK:
+            raise GPError(st, "gp_model_scores")
+        return out[:self.n]
+
     def profile(self, on: bool = True):
         """Start (or stop) per-launch event timing on this handle."""
         _lib.gp_profile_enable(self._h, 1 if on else 0)
@@ -256,6 +290,18 @@ class Batch:
             raise GPError(st, "gp_batch_create")
         self._h = h
 
+    def export(self, rec=None, xadj=None, vwgt=None, part=None, adjncy=None, adjwgt=None):
+        """Export every graph's coarsest level during later calls (device tensors);
+        rec=None turns it off."""
+        if rec is None:
+            st = _lib.gp_batch_export(self._h, None, None, None, None, 0, None, None, 0)
+        else:
+            st = _lib.gp_batch_export(self._h, _ptr(rec), _ptr(xadj), _ptr(vwgt), _ptr(part),
+                                      int(xadj.numel()), _ptr(adjncy), _ptr(adjwgt),
+                                      int(adjncy.numel()))
+        if st != OK:
+            raise GPError(st, "gp_batch_export")
+
     def config(self, workgroups: int = 0, chunk: int = 1, order_mode: int = 0):
         st = _lib.gp_batch_config(self._h, workgroups, chunk, order_mode)
         if st != OK:
@@ -296,3 +342,86 @@ def batch_to_device(b, device="cuda"):
     return (b.G, t(b.voff, np.int64), t(b.eoff, np.int64), t(b.xadj, np.int32),
             t(b.adjncy, np.int32), t(b.adjwgt, np.int64),
             t(np.ascontiguousarray(b.vwgt).reshape(-1), np.int64))
+
+
+NPARAM = 25153
+
+
+class Model:
+    """Device copy of the learned proposal's BF16 parameters (gp_model_create)."""
+
+    def __init__(self, params_bf16_bits: np.ndarray):
+        p = np.ascontiguousarray(params_bf16_bits, dtype=np.uint16)
+        if p.size != NPARAM:
+            raise ValueError(f"expected {NPARAM} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        st = _lib.gp_model_create(_ptr(p), NPARAM, ctypes.byref(h))
+        if st != OK:
+            raise GPError(st, "gp_model_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gp_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trainer:
+    """GPU trainer of the learned proposal (gp_train_*)."""
+
+    def __init__(self, init_params_f32: np.ndarray, stream=None):
+        p = np.ascontiguousarray(init_params_f32, dtype=np.float32)
+        self.stream = stream if stream is not None else _current_stream()
+        h = ctypes.c_void_p()
+        st = _lib.gp_train_create(ctypes.byref(h), _ptr(p), p.size, self.stream)
+        if st != OK:
+            raise GPError(st, "gp_train_create")
+        self._h = h
+
+    def set_data(self, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, labels, balance_on=0):
+        self._keep = (voff, eoff, xadj, adjncy, adjwgt, vwgt, labels)
+        st = _lib.gp_train_set_data(self._h, int(G), _ptr(voff), _ptr(eoff), _ptr(xadj),
+                                    _ptr(adjncy), _ptr(adjwgt), _ptr(vwgt), _ptr(labels),
+                                    int(balance_on))
+        if st != OK:
+            raise GPError(st, "gp_train_set_data")
+
+    def step(self, g0: int, g1: int, lr: float) -> float:
+        loss = ctypes.c_float(0)
+        st = _lib.gp_train_step(self._h, int(g0), int(g1), float(lr), ctypes.byref(loss))
+        if st != OK:
+            raise GPError(st, "gp_train_step")
+        return loss.value
+
+    def grad(self, g0: int, g1: int):
+        g = np.zeros(NPARAM, np.float32)
+        loss = ctypes.c_float(0)
+        st = _lib.gp_train_grad(self._h, int(g0), int(g1), _ptr(g), ctypes.byref(loss))
+        if st != OK:
+            raise GPError(st, "gp_train_grad")
+        return loss.value, g
+
+    def params(self):
+        f = np.zeros(NPARAM, np.float32)
+        b = np.zeros(NPARAM, np.uint16)
+        st = _lib.gp_train_params(self._h, _ptr(f), _ptr(b))
+        if st != OK:
+            raise GPError(st, "gp_train_params")
+        return f, b
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gp_train_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

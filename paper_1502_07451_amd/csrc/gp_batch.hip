@@ -37,6 +37,23 @@ struct LevelRec {
   int8_t* part;
 };
 
+// optional export of every graph's coarsest level and its plain bisection
+// (training data of the learned proposal).  rec[4g..4g+3] = n, 2m, vertex
+// slot, entry slot (or -1 when the export buffers are full); graph g's xadj
+// (n+1 local offsets), vwgt (n x 2) and part (n) sit at its vertex slot,
+// adjncy and adjwgt at its entry slot.
+struct ExportArgs {
+  int64_t* rec;
+  unsigned long long* head_v;
+  unsigned long long* head_e;
+  int32_t* xadj;
+  int64_t* vwgt;
+  int8_t* part;
+  int32_t* adj;
+  int64_t* w;
+  uint64_t cap_v, cap_e;
+};
+
 struct BatchArgs {
   int32_t G;
   const int64_t* voff;
@@ -61,6 +78,7 @@ struct BatchArgs {
   int32_t nmax;
   int32_t nnzmax;
   int32_t chunk;
+  ExportArgs ex;  // ex.rec == nullptr: no export
 };
 
 // per-workgroup scratch carved from wgs + blockIdx.x * wgs_stride
@@ -393,6 +411,34 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     }
     if (cl.n <= kTrialLdsMax) b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, ws.tpart, ws.tres, cl.part);
     __syncthreads();
+    if (a.ex.rec) {
+      __shared__ long long s_vs, s_es;
+      if (threadIdx.x == 0) {
+        const uint64_t vs = atomicAdd(a.ex.head_v, (unsigned long long)(cl.n + 1));
+        const uint64_t es = atomicAdd(a.ex.head_e, (unsigned long long)cl.nnz);
+        const bool ok = vs + cl.n + 1 <= a.ex.cap_v && es + cl.nnz <= a.ex.cap_e;
+        s_vs = ok ? (long long)vs : -1;
+        s_es = ok ? (long long)es : -1;
+        a.ex.rec[4 * g + 0] = cl.n;
+        a.ex.rec[4 * g + 1] = cl.nnz;
+        a.ex.rec[4 * g + 2] = s_vs;
+        a.ex.rec[4 * g + 3] = s_es;
+      }
+      __syncthreads();
+      if (s_vs >= 0) {
+        for (int32_t v = threadIdx.x; v <= cl.n; v += kBlock) a.ex.xadj[s_vs + v] = cl.xadj[v];
+        for (int32_t v = threadIdx.x; v < cl.n; v += kBlock) {
+          a.ex.vwgt[2 * (s_vs + v)] = cl.vc[v];
+          a.ex.vwgt[2 * (s_vs + v) + 1] = cl.vg[v];
+          a.ex.part[s_vs + v] = cl.part[v];
+        }
+        for (int32_t q = threadIdx.x; q < cl.nnz; q += kBlock) {
+          a.ex.adj[s_es + q] = cl.adj[q];
+          a.ex.w[s_es + q] = cl.w[q];
+        }
+      }
+      __syncthreads();
+    }
   }
   // ---- uncoarsening with refinement
   for (int l = L - 1; l >= 0; l--) {
@@ -466,10 +512,14 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   }
 }
 
-__global__ void k_batch_reset(uint32_t* head, unsigned long long* arena_off) {
+__global__ void k_batch_reset(uint32_t* head, unsigned long long* arena_off, ExportArgs ex) {
   if (threadIdx.x == 0) {
     *head = 0;
     *arena_off = 0;
+    if (ex.rec) {
+      *ex.head_v = 0;
+      *ex.head_e = 0;
+    }
   }
 }
 
@@ -522,6 +572,8 @@ struct gp_batch {
   int64_t* hoff = nullptr;    // pinned voff | eoff
   size_t hoff_cap = 0;
   double arena_factor = 3.0;
+  ExportArgs ex;        // export of coarsest levels (rec == nullptr: off)
+  HBuf<unsigned long long> ex_heads;
   // captured launch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -534,6 +586,7 @@ struct gp_batch {
     if (graph) (void)hipGraphDestroy(graph);
     wgs.release(); arena.release(); order.release(); res.release(); head.release();
     arena_off.release();
+    ex_heads.release();
     if (hres) (void)hipHostFree(hres);
     if (hoff) (void)hipHostFree(hoff);
   }
@@ -572,7 +625,7 @@ static gp_status batch_launch(gp_batch* b, BatchArgs a, int nwg) {
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GP_EDEVICE;
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-      k_batch_reset<<<1, 64, 0, cs>>>(a.head, a.arena_off);
+      k_batch_reset<<<1, 64, 0, cs>>>(a.head, a.arena_off, a.ex);
       k_batch<<<nwg, kBlock, dyn, cs>>>(a);
       ok = hipStreamEndCapture(cs, &b->graph) == hipSuccess;
     }
@@ -617,6 +670,29 @@ void gp_batch_destroy(gp_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   delete b;
+}
+
+gp_status gp_batch_export(gp_batch* b, int64_t* rec, int32_t* xadj, int64_t* vwgt, int8_t* part,
+                          int64_t cap_vertices, int32_t* adjncy, int64_t* adjwgt,
+                          int64_t cap_entries) {
+  if (!b) return GP_EINVAL;
+  memset(&b->ex, 0, sizeof(b->ex));
+  b->have_exec = false;
+  if (!rec) return GP_OK;
+  if (!xadj || !vwgt || !part || !adjncy || !adjwgt || cap_vertices < 0 || cap_entries < 0)
+    return GP_EINVAL;
+  if (!b->ex_heads.ensure(2)) return GP_ENOMEM;
+  b->ex.rec = rec;
+  b->ex.head_v = b->ex_heads.p;
+  b->ex.head_e = b->ex_heads.p + 1;
+  b->ex.xadj = xadj;
+  b->ex.vwgt = vwgt;
+  b->ex.part = part;
+  b->ex.adj = adjncy;
+  b->ex.w = adjwgt;
+  b->ex.cap_v = (uint64_t)cap_vertices;
+  b->ex.cap_e = (uint64_t)cap_entries;
+  return GP_OK;
 }
 
 gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode) {
@@ -723,6 +799,7 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   a.nmax = (int32_t)nmax;
   a.nnzmax = (int32_t)nnzmax;
   a.chunk = b->chunk;
+  a.ex = b->ex;
   if ((st = batch_launch(b, a, nwg)) != GP_OK) return st;
   if (hipMemcpyAsync(b->hres, b->res.p, sizeof(gp_result) * G, hipMemcpyDeviceToHost, s) !=
           hipSuccess ||

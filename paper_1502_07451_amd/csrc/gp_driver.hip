@@ -15,6 +15,7 @@
 
 #include "../../include/gp.h"
 #include "gp_launch.h"
+#include "gp_mpnn.h"
 
 using namespace gpk;
 
@@ -98,6 +99,10 @@ struct gp_graph {
   DBuf<int8_t> i_part;
   DBuf<int32_t> i_adjc;
   DBuf<Cand> i_list;
+  // learned proposal scratch
+  DBuf<uint16_t> m_ha, m_hb;
+  DBuf<float> m_inv, m_score;
+  DBuf<int32_t> m_order;
   Ctrl* ctrl = nullptr;
   Ctrl* hctrl = nullptr;  // pinned
   // profiling
@@ -154,6 +159,7 @@ struct gp_graph {
     tmpv.release(); list.release();
     i_tot.release(); i_conn.release(); i_res.release(); i_ctl.release(); i_part.release();
     i_adjc.release(); i_list.release();
+    m_ha.release(); m_hb.release(); m_inv.release(); m_score.release(); m_order.release();
     if (ctrl) (void)hipFree(ctrl);
     if (hctrl) (void)hipHostFree(hctrl);
     for (int i = 0; i < prof.npool; i++)
@@ -242,7 +248,10 @@ static gp_status check_options(const gp_options* o) {
   if (o->coarsen_to < 1 || o->match_rounds < 0 || o->match_rounds > kMaxRounds ||
       o->refine_passes < 0 || o->refine_passes > 64 || o->init_trials < 1 || o->init_trials > 64)
     return GP_EINVAL;
-  if ((o->flags & GP_LEARNED) && !o->model) return GP_EMODEL;
+  if (o->flags & GP_LEARNED) {
+    const MpModel* m = (const MpModel*)o->model;
+    if (!m || m->magic != kMpMagic) return GP_EMODEL;
+  }
   return GP_OK;
 }
 
@@ -463,7 +472,6 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     *res = r;
     return GP_OK;
   }
-  if (o->flags & GP_LEARNED) return GP_EMODEL;  // the learned proposal has its own entry
   hipStream_t s = g->stream;
   if (!g->ensure_scratch()) return GP_ENOMEM;
   const int64_t C = o->coarsen_to;
@@ -521,6 +529,15 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     const int gs = o->ratio[0] <= o->ratio[1] ? 0 : 1;
     g->prof.level = L;
     LCHK(launch_init(cl->view(bal), K, gs, P, g->ctrl, g->init_scratch(), cl->part.p, s));
+    if ((o->flags & GP_LEARNED) && cl->n > 0 && cl->n <= kMpMaxN) {
+      const size_t nh = (size_t)cl->n * kMpH;
+      if (!g->m_ha.ensure(nh) || !g->m_hb.ensure(nh) || !g->m_inv.ensure(cl->n) ||
+          !g->m_score.ensure(cl->n) || !g->m_order.ensure(cl->n))
+        return GP_ENOMEM;
+      MpScratch ms{g->m_ha.p, g->m_hb.p, g->m_inv.p, g->m_score.p, g->m_order.p};
+      LCHK(launch_mpnn(cl->view(bal), cl->vc.p, cl->vg.p, o->model, g->i_tot.p, gs, P, g->ctrl,
+                       ms, cl->part.p, s));
+    }
   }
   auto record = [&](int l, bool coarsest) -> gp_status {
     if (!trace || l >= trace_cap) return GP_OK;
@@ -571,9 +588,27 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   r.time[1] = h.res_time[1];
   r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
   r.levels = L;
-  r.used_learned = 0;
+  r.used_learned = h.used_learned;
   r.status = GP_OK;
   *res = r;
+  return GP_OK;
+}
+
+gp_status gp_model_scores(const void* model, gp_graph* g, float* scores) {
+  const MpModel* m = (const MpModel*)model;
+  if (!g || !m || m->magic != kMpMagic || (g->n > 0 && !scores)) return GP_EINVAL;
+  if (g->n == 0) return GP_OK;
+  Level* l0 = g->lv[0];
+  const size_t nh = (size_t)g->n * kMpH;
+  if (!g->m_ha.ensure(nh) || !g->m_hb.ensure(nh) || !g->m_inv.ensure(g->n) ||
+      !g->m_score.ensure(g->n) || !g->m_order.ensure(g->n))
+    return GP_ENOMEM;
+  MpScratch ms{g->m_ha.p, g->m_hb.p, g->m_inv.p, g->m_score.p, g->m_order.p};
+  LCHK(launch_mpnn_scores(l0->view(0), l0->vc.p, l0->vg.p, model, ms, g->stream));
+  const hipMemcpyKind k = (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost
+                                                     : hipMemcpyDeviceToDevice;
+  HIPCHK(hipMemcpyAsync(scores, ms.score, sizeof(float) * g->n, k, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
   return GP_OK;
 }
 

@@ -68,6 +68,7 @@ struct Ctrl {
   int32_t niso;           // unmatched vertices without neighbours
   uint32_t ctr_iso;
   int32_t lvl_pass[kMaxLevels + 1];  // refinement passes run on each level
+  int32_t used_learned;              // the learned proposal replaced the plain one
   // result of the final statistics kernel
   int64_t res_ext, res_load[2], res_time[2];
   // validation

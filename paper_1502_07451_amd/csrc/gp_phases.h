@@ -1056,6 +1056,72 @@ constexpr int kTrialLdsMax = 3072;
 
 __device__ __forceinline__ size_t trial_lds_bytes(int32_t n) { return (size_t)n * 19 + 16; }
 
+// Refinement passes on an LDS-resident state (gain, balance weight, side,
+// move flag per vertex); gains are updated incrementally (see above).
+template <int BS>
+__device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* s_b,
+                           int8_t* s_part, int8_t* s_mv, RefCtl& srf, SelShared& sel) {
+  const int32_t n = lv.n;
+  __shared__ int64_t sml[BS / 64];
+  for (;;) {
+    if (srf.done) break;
+    int mode, s;
+    plan_pass(srf, &mode, &s);
+    const LdsItems items{s_gain, s_b, s_part, n, s, mode};
+    int64_t cb = 0, cnt = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      Cand c;
+      if (!items.get(v, c)) continue;
+      cb += c.b;
+      cnt++;
+      gmn = c.gain < gmn ? c.gain : gmn;
+      gmx = c.gain > gmx ? c.gain : gmx;
+    }
+    cb = block_sum<BS, int64_t>(cb, sml);
+    cnt = block_sum<BS, int64_t>(cnt, sml);
+    gmn = block_min<BS, int64_t>(gmn, sml);
+    gmx = block_max<BS, int64_t>(gmx, sml);
+    if (threadIdx.x == 0) {
+      srf.mode = mode;
+      srf.s = s;
+    }
+    __syncthreads();
+    decide_admission<BS>(&srf, items, (uint32_t)cnt, cb, gmn, gmx, n, &sel);
+    __syncthreads();
+    const int d = 1 - s;
+    int64_t mb = 0, mn = 0;
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      Cand c;
+      if (items.get(v, c) && admitted(srf, c)) {
+        s_mv[v] = 1;
+        mb += c.b;
+        mn++;
+      }
+    }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS)
+      if (s_mv[v]) {
+        s_part[v] = (int8_t)d;
+        s_gain[v] = -s_gain[v];
+      }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS)
+      if (s_mv[v]) {
+        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
+          const int32_t y = lv.adj[e];
+          const int64_t w = lv.w[e];
+          atomicAdd((unsigned long long*)&s_gain[y],
+                    (unsigned long long)(s_part[y] == d ? -2 * w : 2 * w));
+        }
+        s_mv[v] = 0;
+      }
+    mb = block_sum<BS, int64_t>(mb, sml);
+    mn = block_sum<BS, int64_t>(mn, sml);
+    if (threadIdx.x == 0) finish_pass(&srf, mb, mn);
+    __syncthreads();
+  }
+}
+
 // Trial t of K on an LDS-resident copy of the coarsest graph; writes its
 // cut, infeasibility, loads and assignment to tres / tctl / tpart.
 // lds: trial_lds_bytes(n) bytes; sel, srf: block-shared scratch.
@@ -1136,64 +1202,7 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     start_level(&srf, npass);
   }
   __syncthreads();
-  // refinement passes on the LDS state
-  for (;;) {
-    if (srf.done) break;
-    int mode, s;
-    plan_pass(srf, &mode, &s);
-    const LdsItems items{s_gain, s_b, s_part, n, s, mode};
-    int64_t cb = 0, cnt = 0, gmn = INT64_MAX, gmx = INT64_MIN;
-    for (int32_t v = threadIdx.x; v < n; v += BS) {
-      Cand c;
-      if (!items.get(v, c)) continue;
-      cb += c.b;
-      cnt++;
-      gmn = c.gain < gmn ? c.gain : gmn;
-      gmx = c.gain > gmx ? c.gain : gmx;
-    }
-    cb = block_sum<BS, int64_t>(cb, sml);
-    cnt = block_sum<BS, int64_t>(cnt, sml);
-    gmn = block_min<BS, int64_t>(gmn, sml);
-    gmx = block_max<BS, int64_t>(gmx, sml);
-    if (threadIdx.x == 0) {
-      srf.mode = mode;
-      srf.s = s;
-    }
-    __syncthreads();
-    decide_admission<BS>(&srf, items, (uint32_t)cnt, cb, gmn, gmx, n, &sel);
-    __syncthreads();
-    const int d = 1 - s;
-    int64_t mb = 0, mn = 0;
-    for (int32_t v = threadIdx.x; v < n; v += BS) {
-      Cand c;
-      if (items.get(v, c) && admitted(srf, c)) {
-        s_mv[v] = 1;
-        mb += c.b;
-        mn++;
-      }
-    }
-    __syncthreads();
-    for (int32_t v = threadIdx.x; v < n; v += BS)
-      if (s_mv[v]) {
-        s_part[v] = (int8_t)d;
-        s_gain[v] = -s_gain[v];
-      }
-    __syncthreads();
-    for (int32_t v = threadIdx.x; v < n; v += BS)
-      if (s_mv[v]) {
-        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
-          const int32_t y = lv.adj[e];
-          const int64_t w = lv.w[e];
-          atomicAdd((unsigned long long*)&s_gain[y],
-                    (unsigned long long)(s_part[y] == d ? -2 * w : 2 * w));
-        }
-        s_mv[v] = 0;
-      }
-    mb = block_sum<BS, int64_t>(mb, sml);
-    mn = block_sum<BS, int64_t>(mn, sml);
-    if (threadIdx.x == 0) finish_pass(&srf, mb, mn);
-    __syncthreads();
-  }
+  lds_refine<BS>(lv, s_gain, s_b, s_part, s_mv, srf, sel);
   // cut = sum over v of (gain + tot) / 4
   int64_t q = 0;
   for (int32_t v = threadIdx.x; v < n; v += BS) q += s_gain[v] + tot[v];
