@@ -63,7 +63,8 @@ def _load():
 
 
 def _p(a: np.ndarray):
-    return ctypes.c_void_p(a.ctypes.data)
+    """Host pointer of a; the pointer object keeps a alive until the call returns."""
+    return a.ctypes.data_as(ctypes.c_void_p)
 
 
 @dataclass

@@ -118,6 +118,18 @@ gp_status gp_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result
 gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
                              int64_t* trace, int32_t trace_cap);
 
+/* Copies level `level` (0 = the input graph) of the last gp_partition /
+ * gp_partition_trace on g to host memory: its vertex count and entry count,
+ * CSR (xadj n+1, adjncy and adjwgt nnz), vertex weights (n x 2: cpu, gpu),
+ * the matching that built the next level (n; only below the coarsest level)
+ * and the final bisection of that level (n).  Every output may be NULL.
+ * Blocks until the copies are done.  GP_EINVAL when no partition has run or
+ * the level was not built by it.  For inspecting the multilevel hierarchy
+ * (Section IV-C's coarsening); not needed to partition. */
+gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, int32_t* xadj,
+                        int32_t* adjncy, int64_t* adjwgt, int64_t* vwgt, int32_t* match,
+                        int8_t* part);
+
 void gp_destroy(gp_graph* g);
 
 /* Learned coarsest-level proposal (GP_LEARNED): a 3-layer message-passing

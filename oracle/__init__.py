@@ -69,9 +69,10 @@ def _load():
 
 
 def _p(a):
+    """Host pointer of a; the pointer object keeps a alive until the call returns."""
     if a is None:
         return None
-    return ctypes.c_void_p(a.ctypes.data)
+    return a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _c(a, dt):

@@ -96,6 +96,9 @@ def _load():
     lib.gp_model_free.restype = None
     lib.gp_model_scores.argtypes = [vp, vp, vp]
     lib.gp_model_scores.restype = ctypes.c_int
+    lib.gp_level_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp,
+                                  vp, vp, vp]
+    lib.gp_level_read.restype = ctypes.c_int
     lib.gp_batch_export.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64]
     lib.gp_batch_export.restype = ctypes.c_int
     lib.gp_train_create.argtypes = [ctypes.POINTER(vp), vp, i32, vp]
@@ -121,7 +124,7 @@ EXPORTED = ["gp_options_default", "gp_ratio_from_times", "gp_create", "gp_set_st
             "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror",
             "gp_profile_enable", "gp_profile_read", "gp_batch_create", "gp_batch_config",
             "gp_partition_batch", "gp_batch_destroy", "gp_model_create", "gp_model_free",
-            "gp_model_scores", "gp_batch_export", "gp_train_create", "gp_train_set_data",
+            "gp_model_scores", "gp_level_read", "gp_batch_export", "gp_train_create", "gp_train_set_data",
             "gp_train_step", "gp_train_grad", "gp_train_params", "gp_train_destroy"]
 
 
@@ -155,12 +158,16 @@ def _current_stream():
 
 
 def _ptr(a):
-    """Device pointer of a torch tensor, host pointer of a numpy array."""
+    """Device pointer of a torch tensor, host pointer of a numpy array; the
+    pointer object holds a reference to a, so a temporary argument stays
+    alive until the call returns."""
     if a is None:
         return None
     if isinstance(a, np.ndarray):
-        return ctypes.c_void_p(a.ctypes.data)
-    return ctypes.c_void_p(a.data_ptr())
+        return a.ctypes.data_as(ctypes.c_void_p)
+    p = ctypes.c_void_p(a.data_ptr())
+    p._keep = a
+    return p
 
 
 class Graph:
@@ -216,6 +223,31 @@ class Graph:
         if trace_cap > 0:
             return part, res, tr.reshape(trace_cap, 8)[:res.levels + 1].copy()
         return part, res
+
+    def level(self, level: int) -> dict:
+        """Level `level` of the last partition (host numpy arrays): n, xadj,
+        adjncy, adjwgt, vwgt (n x 2), match (None at the coarsest) and part."""
+        n, nnz = ctypes.c_int32(0), ctypes.c_int64(0)
+        st = _lib.gp_level_read(self._h, int(level), ctypes.byref(n), ctypes.byref(nnz),
+                                None, None, None, None, None, None)
+        if st != OK:
+            raise GPError(st, "gp_level_read")
+        nv, ne = n.value, nnz.value
+        out = dict(n=nv, xadj=np.zeros(nv + 1, np.int32), adjncy=np.zeros(max(ne, 1), np.int32),
+                   adjwgt=np.zeros(max(ne, 1), np.int64), vwgt=np.zeros((max(nv, 1), 2), np.int64),
+                   match=np.full(max(nv, 1), -3, np.int32), part=np.zeros(max(nv, 1), np.int8))
+        st = _lib.gp_level_read(self._h, int(level), None, None, _ptr(out["xadj"]),
+                                _ptr(out["adjncy"]), _ptr(out["adjwgt"]), _ptr(out["vwgt"]),
+                                _ptr(out["match"]), _ptr(out["part"]))
+        if st != OK:
+            raise GPError(st, "gp_level_read")
+        for k in ("adjncy", "adjwgt"):
+            out[k] = out[k][:ne]
+        for k in ("vwgt", "match", "part"):
+            out[k] = out[k][:nv]
+        if nv and out["match"][0] == -3:
+            out["match"] = None
+        return out
 
     def scores(self, model: "Model"):
         """The learned network's score of every vertex (float32[n])."""

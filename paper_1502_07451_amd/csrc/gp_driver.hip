@@ -89,6 +89,7 @@ struct gp_graph {
   int64_t sum[2] = {0, 0};
   int64_t maxv[2] = {0, 0};
   std::vector<Level*> lv;
+  int32_t last_levels = -1;  // coarse levels built by the last partition (-1: none yet)
   // level scratch
   DBuf<int32_t> prop, tile_lead, cmem0, cmem1, cnt, tmpk, longlist;
   DBuf<int64_t> tile_ub, toff, tile_cnt, tmpv;
@@ -588,6 +589,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   r.time[1] = h.res_time[1];
   r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
   r.levels = L;
+  g->last_levels = L;
   r.used_learned = h.used_learned;
   r.status = GP_OK;
   *res = r;
@@ -633,6 +635,30 @@ gp_status gp_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result
 gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
                              int64_t* trace, int32_t trace_cap) {
   return run_partition(g, o, part, res, trace, trace_cap);
+}
+
+gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, int32_t* xadj,
+                        int32_t* adjncy, int64_t* adjwgt, int64_t* vwgt, int32_t* match,
+                        int8_t* part) {
+  if (!g || level < 0 || level > g->last_levels || level >= (int32_t)g->lv.size())
+    return GP_EINVAL;
+  const Level* l = g->lv[level];
+  if (n) *n = l->n;
+  if (nnz) *nnz = l->nnz;
+  hipStream_t s = g->stream;
+  const size_t nv = (size_t)l->n, ne = (size_t)l->nnz;
+  if (xadj) HIPCHK(hipMemcpyAsync(xadj, l->xadj.p, 4 * (nv + 1), hipMemcpyDeviceToHost, s));
+  if (adjncy && ne) HIPCHK(hipMemcpyAsync(adjncy, l->adj.p, 4 * ne, hipMemcpyDeviceToHost, s));
+  if (adjwgt && ne) HIPCHK(hipMemcpyAsync(adjwgt, l->w.p, 8 * ne, hipMemcpyDeviceToHost, s));
+  if (vwgt && nv) {
+    HIPCHK(hipMemcpy2DAsync(vwgt, 16, l->vc.p, 8, 8, nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpy2DAsync(vwgt + 1, 16, l->vg.p, 8, 8, nv, hipMemcpyDeviceToHost, s));
+  }
+  if (match && nv && level < g->last_levels)
+    HIPCHK(hipMemcpyAsync(match, l->match.p, 4 * nv, hipMemcpyDeviceToHost, s));
+  if (part && nv) HIPCHK(hipMemcpyAsync(part, l->part.p, nv, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return GP_OK;
 }
 
 }  // extern "C"

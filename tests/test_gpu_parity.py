@@ -48,11 +48,16 @@ def run_both(gp, g, trace=True, **kw):
 
 def assert_same(ref, got, res, tr=None):
     if tr is not None and len(ref.trace):
-        n = min(len(tr), len(ref.trace))
+        gt, ot = np.asarray(tr), np.asarray(ref.trace)
+        msg = f"gpu trace {gt.tolist()} vs oracle {ot.tolist()}"
+        n = min(len(gt), len(ot))
+        # coarsening columns (n, 2m, pairs) from the top level down, then the
+        # refinement columns from the coarsest level up
+        for l in range(n):
+            assert np.array_equal(gt[l, [0, 1, 7]], ot[l, [0, 1, 7]]), f"level {l}: {msg}"
         for l in range(n - 1, -1, -1):
-            assert np.array_equal(tr[l], ref.trace[l]), (
-                f"level {l}: gpu {tr[l].tolist()} vs oracle {ref.trace[l].tolist()}")
-        assert len(tr) == len(ref.trace)
+            assert np.array_equal(gt[l], ot[l]), f"level {l}: {msg}"
+        assert len(gt) == len(ot), msg
     assert res.levels == ref.levels
     assert np.array_equal(got, ref.part), f"{int((got != ref.part).sum())} vertices differ"
     assert res.cut == ref.cut
@@ -61,9 +66,74 @@ def assert_same(ref, got, res, tr=None):
     assert res.feasible == ref.feasible
 
 
+def check_hierarchy(gp, g, **kw):
+    """Every phase of the GPU run against the oracle applied to the GPU's own
+    level graphs: matching (rounds + two-hop + isolated pairs), contraction,
+    initial bisection, projection + refinement.  Names the first phase and
+    level that differ."""
+    go, oo = opts_pair(gp, **kw)
+    say(f"hierarchy {g.name} n={g.n} nnz={g.nnz} opts={kw}")
+    h = gp.create(g)
+    try:
+        _, res = h.partition(go)
+        L = res.levels
+        lv = [h.level(l) for l in range(L + 1)]
+    finally:
+        h.close()
+    bal = oo.balance_on
+    W = int(lv[0]["vwgt"][:, bal].sum())
+    C = oo.coarsen_to
+    cap = (3 * W + 2 * C - 1) // (2 * C)
+    for l in range(L):
+        a, c = lv[l], lv[l + 1]
+        b = a["vwgt"][:, bal]
+        _, m = oracle.match(a["n"], a["xadj"], a["adjncy"], a["adjwgt"], b, cap, oo.seed, l,
+                            oo.match_rounds)
+        bad = np.nonzero(m != a["match"])[0]
+        assert len(bad) == 0, (f"matching differs at level {l} (n={a['n']}): {len(bad)} vertices,"
+                               f" first {bad[:8].tolist()} gpu {a['match'][bad[:8]].tolist()} "
+                               f"oracle {m[bad[:8]].tolist()}")
+        nc, cmap, cx, ca, cw, cvc, cvg = oracle.contract(a["n"], a["xadj"], a["adjncy"],
+                                                         a["adjwgt"], a["vwgt"][:, 0],
+                                                         a["vwgt"][:, 1], m)
+        assert nc == c["n"], f"contraction of level {l}: nc gpu {c['n']} oracle {nc}"
+        assert np.array_equal(cx, c["xadj"]), f"contraction of level {l}: xadj"
+        assert np.array_equal(ca, c["adjncy"]), f"contraction of level {l}: adjncy"
+        assert np.array_equal(cw, c["adjwgt"]), f"contraction of level {l}: adjwgt"
+        assert np.array_equal(cvc, c["vwgt"][:, 0]) and np.array_equal(cvg, c["vwgt"][:, 1]), (
+            f"contraction of level {l}: vertex weights")
+    tgt, maxw = oracle.balance(W, oo.ratio[0], oo.ratio[1], oo.eps_ppm)
+    cl = lv[L]
+    if not (oo.flags & oracle.FLAG_LEARNED):
+        rc, p0, _ = oracle.init_bisect(cl["n"], cl["xadj"], cl["adjncy"], cl["adjwgt"],
+                                       cl["vwgt"][:, bal], oo.ratio, tgt, maxw,
+                                       min(oo.init_trials, cl["n"]), oo.refine_passes)
+        assert rc == 0
+        bad = np.nonzero(p0 != cl["part"])[0]
+        assert len(bad) == 0, f"initial bisection (n={cl['n']}): {len(bad)} vertices differ"
+    for l in range(L - 1, -1, -1):
+        a, c = lv[l], lv[l + 1]
+        m = a["match"]
+        lead = (m < 0) | (np.arange(a["n"]) < m)
+        cid = np.cumsum(lead) - 1
+        cmap = np.where(lead, cid, cid[np.where(m < 0, 0, m)])
+        proj = c["part"][cmap].astype(np.int8)
+        b = a["vwgt"][:, bal]
+        pw = np.array([b[proj == 0].sum(), b[proj == 1].sum()], np.int64)
+        _, pr, _, _ = oracle.refine(a["n"], a["xadj"], a["adjncy"], a["adjwgt"], b, proj, pw,
+                                    maxw, oo.refine_passes)
+        bad = np.nonzero(pr[:a["n"]] != a["part"])[0]
+        assert len(bad) == 0, f"refinement at level {l} (n={a['n']}): {len(bad)} vertices differ"
+
+
 def test_cholesky8(gp):
     g = dagen.config_cholesky8()
     assert_same(*run_both(gp, g))
+
+
+@pytest.mark.parametrize("which", [0, 1], ids=["cholesky64", "lu48"])
+def test_hierarchy_cholesky64_lu48(gp, which):
+    check_hierarchy(gp, dagen.config_cholesky64_lu48()[which], ratio=(1, 4), eps_ppm=30000)
 
 
 @pytest.mark.parametrize("which", [0, 1], ids=["cholesky64", "lu48"])
