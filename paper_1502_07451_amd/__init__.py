@@ -60,6 +60,10 @@ class ProfRow(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python paper_1502_07451_amd/build.py`")
+    # torch first: its HIP runtime then satisfies libgp.so's, so device
+    # pointers and streams from torch are valid in the library (loading
+    # libgp.so first would pull in a second copy of the runtime)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.gp_options_default.argtypes = [ctypes.POINTER(Options)]

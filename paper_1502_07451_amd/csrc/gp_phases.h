@@ -551,7 +551,8 @@ __device__ __forceinline__ void b_contract_compact(const Ctrl* ctrl,
       cxadj[c] = (int32_t)(base + ex);
       srow[threadIdx.x] = ex;
     }
-    if (c == nc - 1) cxadj[nc] = (int32_t)(base + ex + k);
+    // only the thread that owns row nc - 1 in this tile writes the end offset
+    if (threadIdx.x < kTileC && c == nc - 1) cxadj[nc] = (int32_t)(base + ex + k);
     __syncthreads();
     const int32_t rows = (c0 + kTileC < nc ? kTileC : nc - c0);
     // copy: 16-lane teams over rows

@@ -1,0 +1,336 @@
+"""Training and evaluation of the learned coarsest-level proposal.
+
+The network (3 message-passing layers, hidden size 64, BF16 weights) scores
+the vertices of the coarsest graph; the proposal fills the grown side in
+score order and the exact refinement runs after it, while the plain
+greedy-growing bisection stays both the fallback and the judge.  It is
+trained on what the plain pipeline itself produces: every training DAG is
+partitioned by the batched GPU pipeline with the coarsest-level export on,
+and the label of a coarsest vertex is its side in the refined plain
+bisection (1 = on the grown side).  The partition model is the paper's
+(Section IV-C: weighted task graph, two parts with target shares from
+Eq. (1)-(2)); the network is an extension of the initial partitioning step.
+
+Every step runs in libgp.so: the batched partition and the export
+(gp_partition_batch, gp_batch_export), the training (gp_train_*), and the
+evaluation (gp_partition with GP_LEARNED).  This module only builds inputs,
+repacks the exported arrays and drives the loop.
+
+    python -m paper_1502_07451_amd.learn --graphs 100000 --epochs 4 \\
+        --out paper_1502_07451_amd/mpnn_weights.bin
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+WEIGHTS_PATH = os.path.join(_HERE, "mpnn_weights.bin")
+H = 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ weights
+def param_layout():
+    """(name, shape) of every tensor of the parameter blob, in blob order."""
+    out = [("win", (H, 4)), ("b_in", (H,))]
+    for l in range(3):
+        out += [(f"ws{l}", (H, H)), (f"wn{l}", (H, H)), (f"b{l}", (H,))]
+    out += [("wo", (H,)), ("bo", (1,))]
+    return out
+
+
+def split_params(p: np.ndarray) -> dict:
+    out, o = {}, 0
+    for name, shape in param_layout():
+        k = int(np.prod(shape))
+        out[name] = p[o:o + k].reshape(shape)
+        o += k
+    assert o == p.size
+    return out
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-style initialisation (FP32), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in param_layout():
+        if name.startswith("b"):
+            parts.append(np.zeros(int(np.prod(shape)), np.float32))
+        else:
+            fan_in = shape[-1] if len(shape) == 2 else H
+            if name in ("ws0", "ws1", "ws2", "wn0", "wn1", "wn2"):
+                fan_in = 2 * H
+            std = math.sqrt(2.0 / fan_in)
+            parts.append((rng.standard_normal(int(np.prod(shape))) * std).astype(np.float32))
+    p = np.concatenate(parts)
+    assert p.size == 25153
+    return p
+
+
+def save_weights(path: str, bf16: np.ndarray, meta: dict | None = None):
+    """Raw little-endian uint16 blob (+ a .json next to it with the run's summary)."""
+    np.ascontiguousarray(bf16, np.uint16).tofile(path)
+    if meta is not None:
+        with open(os.path.splitext(path)[0] + ".json", "w") as f:
+            json.dump(meta, f, indent=1, sort_keys=True)
+
+
+def load_weights(path: str = WEIGHTS_PATH) -> np.ndarray:
+    p = np.fromfile(path, dtype=np.uint16)
+    if p.size != 25153:
+        raise ValueError(f"{path}: {p.size} parameters, expected 25153")
+    return p
+
+
+# ------------------------------------------------------------- training set
+@dataclass
+class TrainSet:
+    """Coarsest graphs in the batched layout (device tensors) plus labels."""
+    G: int
+    voff: object
+    eoff: object
+    xadj: object
+    adjncy: object
+    adjwgt: object
+    vwgt: object
+    labels: object
+    n_vertices: int
+    n_entries: int
+
+
+def _gen_batch(args):
+    import dagen
+    G, lo, hi, seed = args
+    return dagen.concat(dagen.batch(G, lo, hi, seed))
+
+
+def export_coarsest(bb, opts, device, batch_ctx=None):
+    """Partitions one concatenated batch on the GPU with the coarsest-level
+    export on; returns the exported graphs as host arrays:
+    list of (n, xadj, adjncy, adjwgt, vwgt n x 2, part)."""
+    import torch
+    import paper_1502_07451_amd as gp
+    dev = gp.batch_to_device(bb, device)
+    G = bb.G
+    nv = int(bb.voff[-1]) + G
+    ne = int(bb.eoff[-1])
+    rec = torch.full((4 * G,), -1, dtype=torch.int64, device=device)
+    ex_x = torch.empty(nv, dtype=torch.int32, device=device)
+    ex_vw = torch.empty(2 * nv, dtype=torch.int64, device=device)
+    ex_p = torch.empty(nv, dtype=torch.int8, device=device)
+    ex_a = torch.empty(max(ne, 1), dtype=torch.int32, device=device)
+    ex_w = torch.empty(max(ne, 1), dtype=torch.int64, device=device)
+    part = torch.empty(int(bb.voff[-1]), dtype=torch.int8, device=device)
+    bt = batch_ctx if batch_ctx is not None else gp.Batch()
+    bt.export(rec, ex_x, ex_vw, ex_p, ex_a, ex_w)
+    try:
+        _, res = bt.partition(*dev, opts=opts, part=part)
+    finally:
+        bt.export(None)
+        if batch_ctx is None:
+            bt.close()
+    torch.cuda.synchronize()
+    bad = [g for g, r in enumerate(res) if r.status != 0]
+    if bad:
+        raise RuntimeError(f"batch partition failed on graphs {bad[:8]}")
+    rec = rec.cpu().numpy().reshape(G, 4)
+    if (rec[:, 2] < 0).any():
+        raise RuntimeError("export buffers too small")
+    hx, hvw = ex_x.cpu().numpy(), ex_vw.cpu().numpy().reshape(-1, 2)
+    hp, ha, hw = ex_p.cpu().numpy(), ex_a.cpu().numpy(), ex_w.cpu().numpy()
+    out = []
+    for g in range(G):
+        n, m, vs, es = (int(x) for x in rec[g])
+        out.append((n, hx[vs:vs + n + 1].copy(), ha[es:es + m].copy(), hw[es:es + m].copy(),
+                    hvw[vs:vs + n].copy(), hp[vs:vs + n].copy()))
+    return out
+
+
+def build_training_set(n_graphs: int, opts=None, lo: float = 2000.0, hi: float = 40000.0,
+                       seed: int = 1, per_batch: int = 4096, device="cuda", workers: int = 8,
+                       pool=None) -> TrainSet:
+    """Generates n_graphs DAGs (even: tiled Cholesky, odd: random layered,
+    log-uniform sizes in [lo, hi]), partitions them in batches on the GPU and
+    keeps each coarsest graph with its plain refined bisection as labels."""
+    import torch
+    import paper_1502_07451_amd as gp
+    opts = opts if opts is not None else gp.options(ratio=(1, 4), eps_ppm=30000)
+    gs = 0 if opts.ratio[0] <= opts.ratio[1] else 1
+    jobs = []
+    left, k = n_graphs, 0
+    while left > 0:
+        G = min(per_batch, left)
+        jobs.append((G, lo, hi, seed * 1000003 + k))
+        left -= G
+        k += 1
+    items = []
+    bt = gp.Batch()
+    it = pool.imap(_gen_batch, jobs) if pool is not None else map(_gen_batch, jobs)
+    t0 = time.perf_counter()
+    for i, bb in enumerate(it):
+        items += export_coarsest(bb, opts, device, bt)
+        log(f"[train-set] batch {i + 1}/{len(jobs)}: {len(items)} coarsest graphs, "
+            f"{time.perf_counter() - t0:.1f} s")
+        del bb
+    bt.close()
+    # repack into the batched layout
+    G = len(items)
+    voff = np.zeros(G + 1, np.int64)
+    eoff = np.zeros(G + 1, np.int64)
+    for g, it_ in enumerate(items):
+        voff[g + 1] = voff[g] + it_[0]
+        eoff[g + 1] = eoff[g] + len(it_[2])
+    xadj = np.concatenate([it_[1] for it_ in items]).astype(np.int32)
+    adj = np.concatenate([it_[2] for it_ in items]).astype(np.int32)
+    w = np.concatenate([it_[3] for it_ in items]).astype(np.int64)
+    vw = np.concatenate([it_[4] for it_ in items]).astype(np.int64).reshape(-1)
+    lab = (np.concatenate([it_[5] for it_ in items]) == gs).astype(np.int8)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    return TrainSet(G, d(voff), d(eoff), d(xadj), d(adj), d(w), d(vw), d(lab), int(voff[-1]),
+                    int(eoff[-1]))
+
+
+# ----------------------------------------------------------------- training
+def train(ts: TrainSet, params0: np.ndarray, epochs: int = 4, graphs_per_step: int = 256,
+          lr: float = 2e-3, balance_on: int = 0, log_every: int = 50):
+    """Adam over mini-batches of consecutive graphs (the set is generated in a
+    shuffled size order already).  Returns (f32, bf16, history)."""
+    import paper_1502_07451_amd as gp
+    tr = gp.Trainer(params0)
+    try:
+        tr.set_data(ts.G, ts.voff, ts.eoff, ts.xadj, ts.adjncy, ts.adjwgt, ts.vwgt, ts.labels,
+                    balance_on)
+        hist = []
+        steps_per_epoch = (ts.G + graphs_per_step - 1) // graphs_per_step
+        total = epochs * steps_per_epoch
+        step = 0
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            ep_loss, nb = 0.0, 0
+            for s in range(steps_per_epoch):
+                g0 = s * graphs_per_step
+                g1 = min(ts.G, g0 + graphs_per_step)
+                # cosine decay
+                cur = lr * 0.5 * (1.0 + math.cos(math.pi * step / max(total, 1)))
+                loss = tr.step(g0, g1, cur)
+                if not math.isfinite(loss):
+                    raise FloatingPointError(f"loss {loss} at step {step}")
+                ep_loss += loss
+                nb += 1
+                step += 1
+                if log_every and step % log_every == 0:
+                    log(f"[train] step {step}/{total} loss {loss:.5f} "
+                        f"({time.perf_counter() - t0:.1f} s)")
+            hist.append(ep_loss / max(nb, 1))
+            log(f"[train] epoch {ep}: mean loss {hist[-1]:.5f}")
+        f32, bf16 = tr.params()
+        return f32, bf16, hist
+    finally:
+        tr.close()
+
+
+# ---------------------------------------------------------------- gain test
+def gain_test(bf16: np.ndarray, graphs, opts_kw: dict, device="cuda", reps: int = 5) -> list:
+    """Plain vs learned on the same graphs: cut, feasibility, time (median of
+    reps, device-resident inputs) and whether the learned proposal won."""
+    import statistics
+
+    import torch
+    import paper_1502_07451_amd as gp
+    model = gp.Model(bf16)
+    out = []
+    try:
+        for g in graphs:
+            h = gp.create(g, device)
+            part = torch.empty(g.n, dtype=torch.int8, device=device)
+            row = {"graph": g.name, "n": g.n, "edges": g.m}
+            for label, flags in (("plain", 0), ("learned", gp.LEARNED)):
+                o = gp.options(**opts_kw, flags=flags, model=model.handle if flags else None)
+                _, r = h.partition(o, part=part)
+                ts = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, r = h.partition(o, part=part)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                row[label] = {"cut": r.cut, "feasible": r.feasible,
+                              "load": [r.load[0], r.load[1]],
+                              "ms": round(statistics.median(ts) * 1e3, 3),
+                              "used_learned": r.used_learned}
+            row["cut_gain_pct"] = round(100.0 * (row["plain"]["cut"] - row["learned"]["cut"])
+                                        / max(row["plain"]["cut"], 1), 4)
+            out.append(row)
+            h.close()
+    finally:
+        model.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--graphs", type=int, default=100000)
+    ap.add_argument("--lo", type=float, default=2000.0)
+    ap.add_argument("--hi", type=float, default=40000.0)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--graphs-per-step", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--out", default=WEIGHTS_PATH)
+    ap.add_argument("--no-eval", action="store_true")
+    args = ap.parse_args(argv)
+    # the generator pool is forked before anything touches the GPU
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(args.workers) if args.workers > 1 else None
+    try:
+        import torch
+        import dagen
+        import paper_1502_07451_amd as gp
+        torch.cuda.set_device(0)
+        t0 = time.perf_counter()
+        ts = build_training_set(args.graphs, lo=args.lo, hi=args.hi, seed=args.seed, pool=pool)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+    t_data = time.perf_counter() - t0
+    log(f"[train-set] {ts.G} graphs, {ts.n_vertices} vertices, {ts.n_entries} entries, "
+        f"{t_data:.1f} s")
+    t0 = time.perf_counter()
+    f32, bf16, hist = train(ts, init_params(args.seed), epochs=args.epochs,
+                            graphs_per_step=args.graphs_per_step, lr=args.lr)
+    t_train = time.perf_counter() - t0
+    meta = {"graphs": ts.G, "vertices": ts.n_vertices, "entries": ts.n_entries,
+            "sizes": [args.lo, args.hi], "epochs": args.epochs,
+            "graphs_per_step": args.graphs_per_step, "lr": args.lr, "seed": args.seed,
+            "epoch_loss": [round(x, 6) for x in hist], "data_s": round(t_data, 1),
+            "train_s": round(t_train, 1)}
+    if not args.no_eval:
+        evals = [dagen.config_layered1m()] + dagen.config_cholesky64_lu48()[:1]
+        meta["gain_test"] = gain_test(bf16, evals, dict(ratio=(1, 4), eps_ppm=30000))
+        for row in meta["gain_test"]:
+            log(json.dumps(row))
+    save_weights(args.out, bf16, meta)
+    log(f"[train] wrote {args.out}")
+    print(json.dumps(meta), flush=True)
+    del gp
+
+
+if __name__ == "__main__":
+    main()
