@@ -191,7 +191,8 @@ def main():
         pb = torch.empty(int(bb.voff[-1]), dtype=torch.int8, device=dev)
         bt = gp.Batch()
         ob = gp.options(ratio=(1, 4), eps_ppm=30000)
-        _, resb = bt.partition(*dev_b, opts=ob, part=pb)
+        # the autotuner checks every configuration gives identical bytes and keeps the fastest
+        _, resb, chosen, tune_ms = bt.autotune(*dev_b, opts=ob, part=pb, reps=1)
         times = []
         for _ in range(3):
             torch.cuda.synchronize()
@@ -205,9 +206,19 @@ def main():
                             "ms": round(tb * 1e3, 3), "edges_per_s": round(mb / tb, 1),
                             "cut_sum": int(sum(r.cut for r in resb)),
                             "all_ok": all(r.status == 0 for r in resb),
-                            "feasible": int(sum(r.feasible for r in resb))}
+                            "feasible": int(sum(r.feasible for r in resb)),
+                            "autotuned": {"workgroups": chosen[0], "chunk": chosen[1],
+                                          "order_mode": chosen[2],
+                                          "tuning_ms_per_call": round(tune_ms, 3)}}
         bt.close()
         del dev_b, pb
+
+    # learned coarsest-level proposal vs the plain bisection on the step's DAGs
+    wpath = os.path.join(ROOT, "paper_1502_07451_amd", "mpnn_weights.bin")
+    if not args.no_extra and os.path.exists(wpath):
+        from paper_1502_07451_amd import learn
+        out["learned"] = learn.gain_test(learn.load_weights(wpath), graphs,
+                                         dict(ratio=(1, 4), eps_ppm=30000), dev, reps=3)
 
     # CPU baseline: the serial oracle on the same workload, on the host
     if not args.no_cpu:

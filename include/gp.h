@@ -190,6 +190,20 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
                              const int64_t* vwgt, const gp_options* o, int8_t* part,
                              gp_result* res);
 void gp_batch_destroy(gp_batch* b);
+/* Autotuner of the batched path: runs gp_partition_batch with each of 18
+ * configurations (1, 2 or 3 persistent workgroups per compute unit x 1, 2
+ * or 4 graphs per queue pop x largest-first or input order), checks that
+ * every configuration returns byte-identical part and res, times `reps`
+ * calls of each (host wall clock, whole calls), and keeps the fastest in b
+ * for later calls.  chosen (host int32[3], may be NULL) receives workgroups,
+ * chunk, order_mode; ms (may be NULL) its mean time per call.  part and res
+ * hold the result on return.  GP_EDEVICE if two configurations disagree (the
+ * previous configuration is then restored). */
+gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
+                            const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
+                            const int64_t* vwgt, const gp_options* o, int8_t* part,
+                            gp_result* res, int32_t reps, int32_t* chosen, double* ms);
+
 /* Export, during later gp_partition_batch calls, every graph's coarsest
  * graph and its plain (greedy-growing + refinement) bisection - the training
  * data of the learned proposal.  All pointers device memory.  rec: int64[4G]

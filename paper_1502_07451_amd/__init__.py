@@ -103,6 +103,9 @@ def _load():
     lib.gp_level_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp,
                                   vp, vp, vp]
     lib.gp_level_read.restype = ctypes.c_int
+    lib.gp_batch_autotune.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options),
+                                      vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.gp_batch_autotune.restype = ctypes.c_int
     lib.gp_batch_export.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64]
     lib.gp_batch_export.restype = ctypes.c_int
     lib.gp_train_create.argtypes = [ctypes.POINTER(vp), vp, i32, vp]
@@ -128,7 +131,7 @@ EXPORTED = ["gp_options_default", "gp_ratio_from_times", "gp_create", "gp_set_st
             "gp_partition", "gp_partition_trace", "gp_destroy", "gp_strerror",
             "gp_profile_enable", "gp_profile_read", "gp_batch_create", "gp_batch_config",
             "gp_partition_batch", "gp_batch_destroy", "gp_model_create", "gp_model_free",
-            "gp_model_scores", "gp_level_read", "gp_batch_export", "gp_train_create", "gp_train_set_data",
+            "gp_model_scores", "gp_level_read", "gp_batch_export", "gp_batch_autotune", "gp_train_create", "gp_train_set_data",
             "gp_train_step", "gp_train_grad", "gp_train_params", "gp_train_destroy"]
 
 
@@ -358,6 +361,24 @@ class Batch:
         if st != OK:
             raise GPError(st, "gp_partition_batch")
         return part, list(res[:G])
+
+    def autotune(self, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, opts=None, part=None,
+                 reps: int = 3):
+        """gp_batch_autotune: returns (part, results, (workgroups, chunk, order_mode), ms)."""
+        import torch
+        opts = opts or options()
+        if part is None:
+            part = torch.empty(max(int(vwgt.numel()) // 2, 1), dtype=torch.int8,
+                               device=xadj.device)
+        res = (Result * max(G, 1))()
+        chosen = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double(0)
+        st = _lib.gp_batch_autotune(self._h, int(G), _ptr(voff), _ptr(eoff), _ptr(xadj),
+                                    _ptr(adjncy), _ptr(adjwgt), _ptr(vwgt), ctypes.byref(opts),
+                                    _ptr(part), res, int(reps), chosen, ctypes.byref(ms))
+        if st != OK:
+            raise GPError(st, "gp_batch_autotune")
+        return part, list(res[:G]), (chosen[0], chosen[1], chosen[2]), ms.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -830,6 +831,84 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   }
   memcpy(res, b->hres, sizeof(gp_result) * G);
   return GP_OK;
+}
+
+gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
+                            const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
+                            const int64_t* vwgt, const gp_options* o, int8_t* part,
+                            gp_result* res, int32_t reps, int32_t* chosen, double* ms) {
+  if (!b || reps < 1 || G < 0) return GP_EINVAL;
+  if (G == 0) return gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part, res);
+  if (!voff || !part || !res) return GP_EINVAL;
+  const int keep[3] = {b->nwg, b->chunk, b->order_mode};
+  int64_t ntot = 0;
+  if (hipMemcpy(&ntot, voff + G, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return GP_EDEVICE;
+  if (ntot < 0) return GP_EINVAL;
+  const int cus = b->cus > 0 ? b->cus : 256;
+  // persistent workgroups per compute unit x graphs per queue pop x queue order
+  std::vector<int> cand;
+  for (int per_cu : {1, 2, 3})
+    for (int chunk : {1, 2, 4})
+      for (int order : {0, 1}) {
+        cand.push_back(per_cu * cus);
+        cand.push_back(chunk);
+        cand.push_back(order);
+      }
+  const size_t nc = cand.size() / 3;
+  std::vector<int8_t> ref_part((size_t)ntot), cur_part((size_t)ntot);
+  std::vector<gp_result> ref_res((size_t)G), cur_res((size_t)G);
+  double best = 1e300;
+  size_t best_i = 0;
+  gp_status st = GP_OK;
+  for (size_t i = 0; i < nc && st == GP_OK; i++) {
+    b->nwg = cand[3 * i];
+    b->chunk = cand[3 * i + 1];
+    b->order_mode = cand[3 * i + 2];
+    // the first call of a configuration captures its graph; it is not timed
+    st = gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part,
+                            i == 0 ? ref_res.data() : cur_res.data());
+    if (st != GP_OK) break;
+    if (hipMemcpy(i == 0 ? ref_part.data() : cur_part.data(), part, (size_t)ntot,
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+      st = GP_EDEVICE;
+      break;
+    }
+    if (i > 0 && (memcmp(ref_part.data(), cur_part.data(), (size_t)ntot) != 0 ||
+                  memcmp(ref_res.data(), cur_res.data(), sizeof(gp_result) * G) != 0)) {
+      st = GP_EDEVICE;  // a configuration changed a result: never expected
+      break;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps && st == GP_OK; r++)
+      st = gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part,
+                              cur_res.data());
+    const double t =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+        reps;
+    if (st == GP_OK && t < best) {
+      best = t;
+      best_i = i;
+    }
+  }
+  if (st != GP_OK) {
+    b->nwg = keep[0];
+    b->chunk = keep[1];
+    b->order_mode = keep[2];
+    return st;
+  }
+  b->nwg = cand[3 * best_i];
+  b->chunk = cand[3 * best_i + 1];
+  b->order_mode = cand[3 * best_i + 2];
+  if (chosen) {
+    chosen[0] = b->nwg;
+    chosen[1] = b->chunk;
+    chosen[2] = b->order_mode;
+  }
+  if (ms) *ms = best;
+  // leave the caller the chosen configuration's (identical) outputs
+  st = gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part, res);
+  return st;
 }
 
 }  // extern "C"

@@ -152,3 +152,23 @@ def test_batch_full_4096_sampled(gp):
         h.close()
         assert np.array_equal(p.cpu().numpy(), got[b.voff[g]:b.voff[g + 1]])
         assert r.cut == res[g].cut
+
+
+def test_batch_autotune_keeps_results(gp):
+    """Every autotuner configuration must give the same bytes; the chosen
+    one is then used by later calls and still matches the oracle."""
+    graphs = mixed_graphs(23, 60)
+    kw = dict(coarsen_to=64)
+    bb = dagen.concat(graphs)
+    dev = gp.batch_to_device(bb)
+    bt = gp.Batch()
+    say("case batch autotune")
+    part, res, chosen, ms = bt.autotune(*dev, opts=gp.options(**kw), reps=1)
+    say(f"chosen {chosen} {ms:.3f} ms")
+    assert chosen[1] in (1, 2, 4) and chosen[2] in (0, 1) and chosen[0] > 0 and ms > 0
+    got = part.cpu().numpy()
+    check_against_oracle(bb, graphs, got, res, kw)
+    part2, res2 = bt.partition(*dev, opts=gp.options(**kw))
+    assert np.array_equal(part2.cpu().numpy(), got)
+    assert [r.as_dict() for r in res2] == [r.as_dict() for r in res]
+    bt.close()
