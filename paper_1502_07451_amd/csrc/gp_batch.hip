@@ -336,10 +336,10 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     __syncthreads();
     b_contract_count(fv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles, 0, 1);
     __syncthreads();
-    b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,
-                   sc.cmem1, sc.toff, ntiles, 0, 1);
-    __syncthreads();
     const int ntc = (f.n + kTileC - 1) / kTileC;
+    b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,
+                   sc.cmem1, sc.toff, ntiles, sc.tile_cnt, ntc, 0, 1);
+    __syncthreads();
     b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
                     sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1);
     __syncthreads();
@@ -494,7 +494,13 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   __syncthreads();
 }
 
-constexpr size_t kBatchLds = 64 * 1024 - 6 * 1024;  // dynamic LDS of the persistent kernel
+// dynamic LDS of the persistent kernel: the largest phase is an LDS-resident
+// initial-bisection trial (70,932 bytes at 3,072 vertices); two workgroups of
+// 72 KB plus their static LDS fit a compute unit's 160 KB
+constexpr size_t kBatchLds = 72 * 1024;
+static_assert(trial_lds_bytes(kTrialLdsMax, kBlock) <= kBatchLds, "trial state exceeds the LDS");
+static_assert((size_t)kWin * 12 <= kBatchLds && (size_t)kRowBlockCap * 12 <= kBatchLds,
+              "contraction buffers exceed the LDS");
 
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];

@@ -25,31 +25,100 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// ------------------------------------------------------ lane exchange
+// The value of lane (lane ^ O), O in {1, 2, 4, 8, 16, 32}, moved in registers:
+// DPP within 16-lane rows (xor 1 and 2 are quad permutations; xor 4 is the
+// half-row mirror (x ^ 7) followed by the quad reversal (x ^ 3); xor 8 is the
+// row mirror (x ^ 15) followed by the half-row mirror), and the gfx950
+// permlane swaps across rows (16) and wave halves (32).  An LDS permute
+// (ds_bpermute) costs an LDS round trip per step instead.  Every lane of the
+// aligned group of 2 O lanes holding the pair must be active.  O is a
+// template argument so that no step is ever dispatched at run time.
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int O>
+__device__ __forceinline__ int32_t xor_lane32(int32_t v) {
+  static_assert(O == 1 || O == 2 || O == 4 || O == 8 || O == 16 || O == 32, "lane xor");
+  if constexpr (O == 1) {
+    return dpp<0xB1>(v);  // quad_perm(1,0,3,2)
+  } else if constexpr (O == 2) {
+    return dpp<0x4E>(v);  // quad_perm(2,3,0,1)
+  } else if constexpr (O == 4) {
+    return dpp<0x1B>(dpp<0x141>(v));  // half-row mirror, then quad_perm(3,2,1,0)
+  } else if constexpr (O == 8) {
+    return dpp<0x141>(dpp<0x140>(v));  // row mirror, then half-row mirror
+  } else if constexpr (O == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int32_t)((lane_id() & 16) ? p[0] : p[1]);
+  } else {
+    const auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int32_t)((lane_id() & 32) ? p[0] : p[1]);
+  }
+}
+
+template <int O, class T>
+__device__ __forceinline__ T xor_lane(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lane values");
+  if constexpr (sizeof(T) == 4) {
+    int32_t x;
+    __builtin_memcpy(&x, &v, 4);
+    x = xor_lane32<O>(x);
+    T r;
+    __builtin_memcpy(&r, &x, 4);
+    return r;
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    const uint32_t lo = (uint32_t)xor_lane32<O>((int32_t)(uint32_t)u);
+    const uint32_t hi = (uint32_t)xor_lane32<O>((int32_t)(uint32_t)(u >> 32));
+    u = ((uint64_t)hi << 32) | lo;
+    T r;
+    __builtin_memcpy(&r, &u, 8);
+    return r;
+  }
+}
+
+// Butterfly over a team of TW lanes: step(integral O) for O = TW/2, ..., 1.
+template <int O>
+struct LaneXor {
+  static constexpr int value = O;
+};
+
+template <int TW, class F>
+__device__ __forceinline__ void butterfly(F&& step) {
+  if constexpr (TW > 32) step(LaneXor<32>{});
+  if constexpr (TW > 16) step(LaneXor<16>{});
+  if constexpr (TW > 8) step(LaneXor<8>{});
+  if constexpr (TW > 4) step(LaneXor<4>{});
+  if constexpr (TW > 2) step(LaneXor<2>{});
+  if constexpr (TW > 1) step(LaneXor<1>{});
+}
+
 // ----------------------------------------------------------------- teams
 template <int TW, class T>
 __device__ __forceinline__ T team_sum(T v) {
-#pragma unroll
-  for (int o = TW / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TW);
+  butterfly<TW>([&](auto o) { v += xor_lane<decltype(o)::value>(v); });
   return v;
 }
 
 template <int TW, class T>
 __device__ __forceinline__ T team_max(T v) {
-#pragma unroll
-  for (int o = TW / 2; o > 0; o >>= 1) {
-    T u = __shfl_xor(v, o, TW);
+  butterfly<TW>([&](auto o) {
+    const T u = xor_lane<decltype(o)::value>(v);
     v = u > v ? u : v;
-  }
+  });
   return v;
 }
 
 template <int TW, class T>
 __device__ __forceinline__ T team_min(T v) {
-#pragma unroll
-  for (int o = TW / 2; o > 0; o >>= 1) {
-    T u = __shfl_xor(v, o, TW);
+  butterfly<TW>([&](auto o) {
+    const T u = xor_lane<decltype(o)::value>(v);
     v = u < v ? u : v;
-  }
+  });
   return v;
 }
 
@@ -211,11 +280,22 @@ struct LdsItems {
 //   want_ge = 1: threshold of the shortest prefix with weight >= bound (> 0)
 // Returns thr with the prefix = { key >= thr }.  Every thread of the block
 // must call it; BS is the block size.
+//
+// Per digit: a weighted 256-bin histogram of the candidates that share the
+// prefix chosen so far (a wave whose hitting lanes all fall in one bin adds
+// their sum with one atomic, which keeps skewed digits from serialising on
+// one bin), then a block-wide scan over the bins from the top picks the bin
+// where the bound is crossed.
 template <int BS, class Items>
 __device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int tbits,
                               int want_ge, int64_t bound, SelShared* sh) {
+  static_assert(BS % 64 == 0 && (BS >= 256 || 256 % BS == 0), "block of whole waves");
+  constexpr int PER = BS >= 256 ? 1 : 256 / BS;  // histogram bins per thread
+  __shared__ int64_t sm_scan[BS / 64];
+  __shared__ int32_t sm_min[BS / 64];
   const int ndig = (tbits + 7) / 8;
   const uint32_t cnt = items.count();
+  const int lane = lane_id();
   if (threadIdx.x == 0) {
     sh->prefix = 0;
     sh->above = 0;
@@ -225,38 +305,67 @@ __device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int 
   __syncthreads();
   for (int d = ndig - 1; d >= 0; d--) {
     const int shf = 8 * d;
-    for (int i = threadIdx.x; i < 256; i += BS) sh->hist[i] = 0;
+    for (int q = threadIdx.x; q < 256; q += BS) sh->hist[q] = 0;
     __syncthreads();
     const u128 P = sh->prefix;
-    for (uint32_t i = threadIdx.x; i < cnt; i += BS) {
+    // uniform trip count: every lane of a wave takes part in the ballots
+    for (uint32_t base = 0; base < cnt; base += BS) {
+      const uint32_t i = base + threadIdx.x;
       Cand c;
-      if (!items.get(i, c)) continue;
-      u128 k = cand_key(c, gmin, idbits);
-      if ((k >> (shf + 8)) == P)
-        atomicAdd((unsigned long long*)&sh->hist[(int)((k >> shf) & 255)],
-                  (unsigned long long)c.b);
+      c.b = 0;
+      int bkt = -1;
+      if (i < cnt && items.get(i, c)) {
+        const u128 k = cand_key(c, gmin, idbits);
+        if ((k >> (shf + 8)) == P) bkt = (int)((k >> shf) & 255);
+      }
+      const uint64_t hits = __ballot(bkt >= 0);
+      if (hits == 0) continue;
+      const int lead = __builtin_ctzll(hits);
+      const int b0 = __shfl(bkt, lead, 64);
+      if (__ballot(bkt >= 0 && bkt != b0) == 0) {
+        const int64_t sum = team_sum<64, int64_t>(bkt >= 0 ? c.b : 0);
+        if (lane == lead) atomicAdd((unsigned long long*)&sh->hist[b0], (unsigned long long)sum);
+      } else if (bkt >= 0) {
+        atomicAdd((unsigned long long*)&sh->hist[bkt], (unsigned long long)c.b);
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t above = sh->above;
-      int sel = -1;
-      for (int bkt = 255; bkt >= 0; bkt--) {
-        int64_t h = sh->hist[bkt];
-        if (want_ge) {
-          if (above + h >= bound) { sel = bkt; break; }
-          above += h;
-        } else {
-          if (above + h <= bound) above += h;
-          else { sel = bkt; break; }
-        }
+    // thread t looks at bins 255 - j for j in [t*PER, t*PER + PER): the bins
+    // from the top, with running sums
+    const int j0 = (int)threadIdx.x * PER;
+    int64_t hv[PER];
+    int64_t local = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      hv[q] = j0 + q < 256 ? sh->hist[255 - (j0 + q)] : 0;
+      local += hv[q];
+    }
+    int64_t tot;
+    const int64_t ex = block_exscan<BS, int64_t>(local, sm_scan, &tot);
+    const int64_t above0 = sh->above;
+    int64_t run = above0 + ex, at = 0;
+    int first = 1 << 30;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const bool cross = j0 + q < 256 &&
+                         (want_ge ? (run + hv[q] >= bound) : (run + hv[q] > bound));
+      if (cross && first == (1 << 30)) {
+        first = j0 + q;
+        at = run;
       }
-      sh->above = above;
-      if (sel < 0) {  // only for want_ge = 0: every candidate with this prefix fits
-        sh->result = P << (shf + 8);
-        sh->done = 1;
-      } else {
-        sh->prefix = (P << 8) | (u128)(unsigned)sel;
-      }
+      run += hv[q];
+    }
+    const int mine = first;
+    first = block_min<BS, int32_t>(first, sm_min);
+    if (first < 256 && mine == first) {
+      sh->above = at;
+      sh->prefix = (P << 8) | (u128)(unsigned)(255 - first);
+    }
+    if (first >= 256 && threadIdx.x == 0) {
+      // only for want_ge = 0: every candidate with this prefix fits
+      sh->above = above0 + tot;
+      sh->result = P << (shf + 8);
+      sh->done = 1;
     }
     __syncthreads();
     if (sh->done) break;
@@ -276,24 +385,31 @@ __device__ __forceinline__ int bitlen64(uint64_t x) { return x == 0 ? 0 : 64 - _
 // raised on a repeated key (!MERGE).  Key INT_MAX means "drop".
 
 // one element per lane, T lanes, L <= T
+template <int T, int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_step(int32_t& k, int64_t& v) {
+  const int lane = threadIdx.x & (T - 1);
+  const int32_t k2 = xor_lane<STRIDE>(k);
+  const int64_t v2 = xor_lane<STRIDE>(v);
+  const bool up = (lane & SIZE) == 0;
+  const bool lower = (lane & STRIDE) == 0;
+  const bool take = (lower == up) ? (k2 < k) : (k2 > k);
+  if (take) {
+    k = k2;
+    v = v2;
+  }
+  if constexpr (STRIDE > 1) bitonic_step<T, SIZE, STRIDE / 2>(k, v);
+}
+
+template <int T, int SIZE>
+__device__ __forceinline__ void bitonic_stage(int32_t& k, int64_t& v) {
+  bitonic_step<T, SIZE, SIZE / 2>(k, v);
+  if constexpr (SIZE < T) bitonic_stage<T, SIZE * 2>(k, v);
+}
+
+// one element per lane, T lanes, L <= T; ascending keys
 template <int T>
 __device__ __forceinline__ void team_bitonic(int32_t& k, int64_t& v) {
-  const int lane = threadIdx.x & (T - 1);
-#pragma unroll
-  for (int size = 2; size <= T; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      int32_t k2 = __shfl_xor(k, stride, T);
-      int64_t v2 = __shfl_xor(v, stride, T);
-      bool up = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
-      bool take = (lower == up) ? (k2 < k) : (k2 > k);
-      if (take) {
-        k = k2;
-        v = v2;
-      }
-    }
-  }
+  bitonic_stage<T, 2>(k, v);
 }
 
 // after team_bitonic: writes the distinct keys, returns their count

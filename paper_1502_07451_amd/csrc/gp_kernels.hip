@@ -83,8 +83,10 @@ __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int
                                                          const int64_t* tile_ub, int32_t* cmap,
                                                          int64_t* cvc, int64_t* cvg,
                                                          int32_t* cmem0, int32_t* cmem1,
-                                                         int64_t* toff, int ntiles) {
-  b_contract_map(lv, match, vc, vg, tile_lead, tile_ub, cmap, cvc, cvg, cmem0, cmem1, toff, ntiles, (int)blockIdx.x, (int)gridDim.x);
+                                                         int64_t* toff, int ntiles,
+                                                         int64_t* tile_cnt, int ntiles_c) {
+  b_contract_map(lv, match, vc, vg, tile_lead, tile_ub, cmap, cvc, cvg, cmem0, cmem1, toff, ntiles,
+                 tile_cnt, ntiles_c, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_contract_rows(
@@ -379,8 +381,10 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
   KCHECK();
   {
     ProfScope ps(PK_CONTRACT_MAP, 0, 4 * n + 4 * (n + 1) + 16 * n + 4 * n, s);
+    const int ntc = (lv.n + kTileC - 1) / kTileC;
     k_contract_map<<<g, kBlock, 0, s>>>(lv, match, vc, vg, sc.tile_lead, sc.tile_ub, cmap, cvc,
-                                        cvg, sc.cmem0, sc.cmem1, sc.toff, ntiles);
+                                        cvg, sc.cmem0, sc.cmem1, sc.toff, ntiles, sc.tile_cnt,
+                                        ntc > 0 ? ntc : 1);
   }
   KCHECK();
   return true;
@@ -396,14 +400,17 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   {
     // fine rows read once (12 B per entry) plus cmap; coarse rows written once
     ProfScope ps(PK_CONTRACT_ROWS, 0, 12.0 * lv.nnz + 4.0 * lv.n + 4.0 * (lv.n + 1), s);
-    k_contract_rows<<<g, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
+    k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
                                          sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1);
   }
   KCHECK();
   const size_t dyn = (size_t)kWin * (sizeof(int64_t) + sizeof(int32_t));
   {
     ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
-    k_contract_long<<<64, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
+    // rows of more than kWaveCap candidates: one block each (a level of a large
+    // graph can have thousands of them)
+    const int glong = grid_for(nc_max, 512, 1024) < 64 ? 64 : grid_for(nc_max, 512, 1024);
+    k_contract_long<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
                                             sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ntc1);
   }
   KCHECK();
@@ -485,7 +492,15 @@ bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, cons
   KCHECK();
   ProfScope ps(PK_INIT_TRIALS, 0, 0.0, s);
   if (lv.n <= kTrialLdsMax) {
-    const size_t dyn = (size_t)lv.n * 19 + 16;
+    const size_t dyn = trial_lds_bytes(lv.n, kTrialBlock);
+    static bool lds_attr = false;  // more than 64 KB of dynamic LDS must be allowed once
+    if (!lds_attr) {
+      if (hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)trial_lds_bytes(kTrialLdsMax, kTrialBlock)) != hipSuccess)
+        return false;
+      lds_attr = true;
+    }
     k_init_trials_lds<kTrialBlock><<<K, kTrialBlock, dyn, s>>>(lv, is.tot, K, gs, npass, ctrl,
                                                                is.ctl, is.part, is.res, out_part);
     KCHECK();

@@ -84,15 +84,14 @@ __device__ __forceinline__ void b_match_propose(LevelView lv, const int32_t* mat
         bv = v;
       }
     }
-#pragma unroll
-    for (int o = TW / 2; o > 0; o >>= 1) {
-      int64_t ow = __shfl_xor(bw, o, TW);
-      int32_t ov = __shfl_xor(bv, o, TW);
+    butterfly<TW>([&](auto o) {
+      const int64_t ow = xor_lane<decltype(o)::value>(bw);
+      const int32_t ov = xor_lane<decltype(o)::value>(bv);
       if (match_better(ow, ov, bw, bv, hs, u)) {
         bw = ow;
         bv = ov;
       }
-    }
+    });
     if (lane == 0) prop[u] = bv;
   }
 }
@@ -148,15 +147,14 @@ __device__ __forceinline__ void b_hub(LevelView lv, const int32_t* match, int32_
         bv = v;
       }
     }
-#pragma unroll
-    for (int o = TW / 2; o > 0; o >>= 1) {
-      int64_t ow = __shfl_xor(bw, o, TW);
-      int32_t ov = __shfl_xor(bv, o, TW);
+    butterfly<TW>([&](auto o) {
+      const int64_t ow = xor_lane<decltype(o)::value>(bw);
+      const int32_t ov = xor_lane<decltype(o)::value>(bv);
       if (match_better(ow, ov, bw, bv, hs, u)) {
         bw = ow;
         bv = ov;
       }
-    }
+    });
     if (lane == 0) hub[u] = bv;
   }
 }
@@ -334,9 +332,14 @@ __device__ __forceinline__ void b_contract_map(LevelView lv, const int32_t* matc
                                                          const int64_t* tile_ub, int32_t* cmap,
                                                          int64_t* cvc, int64_t* cvg,
                                                          int32_t* cmem0, int32_t* cmem1,
-                                                         int64_t* toff, int ntiles, int bid_, int nblk_) {
+                                                         int64_t* toff, int ntiles, int64_t* tile_cnt,
+                                                         int ntiles_c, int bid_, int nblk_) {
   __shared__ int64_t sml[kBlock / 64];
   __shared__ int32_t smi[kBlock / 64];
+  // coarse-tile entry counts, accumulated by the row sorts that follow
+  for (int64_t i = (int64_t)bid_ * kBlock + threadIdx.x; i < ntiles_c;
+       i += (int64_t)nblk_ * kBlock)
+    tile_cnt[i] = 0;
   for (int t = bid_; t < ntiles; t += nblk_) {
     const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
     int32_t lead = 0;
@@ -429,64 +432,91 @@ __device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32
   if (lane == 0) *cnt_out = cnt;
 }
 
+// Rows are sorted in groups of 16 per block: one 16-lane team per short row
+// (<= 16 candidates), and for longer rows one wave per row (in registers up
+// to 64, in the wave's private LDS up to kWaveCap); rows beyond that go to
+// the long list.  Many small groups keep enough rows in flight to hide the
+// gather latency at the coarse levels, where rows are long and few.
+constexpr int kRowsPerBlock = 16;
+
 __device__ __forceinline__ void b_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
     const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
     int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, unsigned char* lds,
     int bid_, int nblk_) {
-  // lds: kRowBlockCap x (int64 + int32) bytes, split into kBlock/64 wave-private
-  // regions of kWaveCap entries for the wave sorts
+  // lds: kBlock/64 wave-private regions of kWaveCap x (int64 + int32) bytes
   int64_t* sv = (int64_t*)lds;
   int32_t* sk = (int32_t*)(sv + kRowBlockCap);
-  __shared__ int32_t smi[kBlock / 64];
-  __shared__ int64_t sml[kBlock / 64];
+  __shared__ int32_t s_e0[kRowsPerBlock], s_d0[kRowsPerBlock], s_e1[kRowsPerBlock],
+      s_len[kRowsPerBlock];
   static_assert(kWaveCap * (kBlock / 64) <= kRowBlockCap, "wave regions exceed the block region");
+  static_assert(kRowsPerBlock == 16 && kBlock == 256, "16 teams of 16 lanes, 4 rows per wave");
+  static_assert(kTileC % kRowsPerBlock == 0, "row groups nest in compaction tiles");
+  (void)ntiles_c;
   const int32_t nc = ctrl->nc;
   const int wave = threadIdx.x / 64;
-  for (int t = bid_; t < ntiles_c; t += nblk_) {
-    const int32_t c0 = t * kTileC;
-    const int32_t c1 = c0 + kTileC < nc ? c0 + kTileC : nc;
-    // rows of at most 16 candidates: 16-lane teams
-    for (int32_t c = c0 + (int32_t)threadIdx.x / 16; c < c1; c += kBlock / 16) {
-      int L;
-      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
-      if (L <= 16) team_row<16>(ld, L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
-    }
-    // 17..64 candidates: one wave in registers; 65..kWaveCap: one wave in LDS
-    for (int32_t c = c0 + wave; c < c1; c += kBlock / 64) {
-      int L;
-      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
-      if (L > 16 && L <= 64) {
-        team_row<64>(ld, L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
-      } else if (L > 64 && L <= kWaveCap) {
-        bool dummy = false;
-        int k = wave_sort_emit<true>(L, ld, sk + wave * kWaveCap, sv + wave * kWaveCap,
-                                     tmpk + toff[c], tmpv + toff[c], &dummy);
-        if (lane_id() == 0) cnt[c] = k;
-      }
+  const int32_t ngroups = (nc + kRowsPerBlock - 1) / kRowsPerBlock;
+  for (int32_t grp = bid_; grp < ngroups; grp += nblk_) {
+    const int32_t c0 = grp * kRowsPerBlock;
+    const int rows = c0 + kRowsPerBlock < nc ? kRowsPerBlock : nc - c0;
+    if ((int)threadIdx.x < rows) {
+      const int32_t c = c0 + (int32_t)threadIdx.x;
+      const int32_t m0 = cmem0[c], m1 = cmem1[c];
+      const int32_t e0 = lv.xadj[m0], d0 = lv.xadj[m0 + 1] - e0;
+      const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0;
+      const int32_t d1 = m1 >= 0 ? lv.xadj[m1 + 1] - e1 : 0;
+      s_e0[threadIdx.x] = e0;
+      s_d0[threadIdx.x] = d0;
+      s_e1[threadIdx.x] = e1;
+      s_len[threadIdx.x] = d0 + d1;
     }
     __syncthreads();
-    // longer rows: the whole block in LDS, or deferred to the dense merge
-    for (int32_t c = c0; c < c1; c++) {
-      int L;
-      CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
-      if (L <= kWaveCap) continue;
-      if (L <= kRowBlockCap) {
+    auto loader = [&](int i) {
+      CoarseRowLoader ld;
+      ld.xadj = lv.xadj;
+      ld.adj = lv.adj;
+      ld.w = lv.w;
+      ld.cmap = cmap;
+      ld.c = c0 + i;
+      ld.e0 = s_e0[i];
+      ld.d0 = s_d0[i];
+      ld.e1 = s_e1[i];
+      return ld;
+    };
+    {
+      const int i = (int)threadIdx.x / 16;
+      if (i < rows && s_len[i] <= 16) {
+        const int32_t c = c0 + i;
+        team_row<16>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+      }
+    }
+    for (int q = 0; q < 4; q++) {
+      const int i = 4 * wave + q;
+      if (i >= rows) break;
+      const int L = s_len[i];
+      if (L <= 16) continue;
+      const int32_t c = c0 + i;
+      if (L <= 64) {
+        team_row<64>(loader(i), L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+      } else if (L <= kWaveCap) {
         bool dummy = false;
-        int k = block_sort_emit<kBlock, true>(L, ld, sk, sv, tmpk + toff[c], tmpv + toff[c],
-                                              &dummy, smi);
-        if (threadIdx.x == 0) cnt[c] = k;
-      } else if (threadIdx.x == 0) {
-        int slot = atomicAdd(&wctrl->nlong, 1);
+        const int k = wave_sort_emit<true>(L, loader(i), sk + wave * kWaveCap,
+                                           sv + wave * kWaveCap, tmpk + toff[c], tmpv + toff[c],
+                                           &dummy);
+        if (lane_id() == 0) cnt[c] = k;
+      } else if (lane_id() == 0) {
+        const int slot = atomicAdd(&wctrl->nlong, 1);
         longlist[slot] = c;
         cnt[c] = 0;
       }
     }
     __syncthreads();
-    int64_t s = 0;
-    for (int32_t c = c0 + threadIdx.x; c < c1; c += kBlock) s += cnt[c];
-    s = block_sum<kBlock, int64_t>(s, sml);
-    if (threadIdx.x == 0) tile_cnt[t] = s;
+    if (threadIdx.x < 64) {
+      int64_t sum = (int)threadIdx.x < rows ? cnt[c0 + threadIdx.x] : 0;
+      sum = team_sum<64, int64_t>(sum);
+      if (threadIdx.x == 0 && sum)
+        atomicAdd((unsigned long long*)&tile_cnt[c0 / kTileC], (unsigned long long)sum);
+    }
   }
 }
 
@@ -509,8 +539,15 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
     int L;
     CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
     bool dummy = false;
-    int k = block_dense_emit<kBlock, true>(L, ld, acc, cc, smi, sml, tmpk + toff[c],
-                                           tmpv + toff[c], &dummy);
+    int k;
+    if (L <= kSortCap) {
+      // the LDS window doubles as the block sort's buffers
+      k = block_sort_emit<kBlock, true>(L, ld, cc, acc, tmpk + toff[c], tmpv + toff[c], &dummy,
+                                        smi);
+    } else {
+      k = block_dense_emit<kBlock, true>(L, ld, acc, cc, smi, sml, tmpk + toff[c],
+                                         tmpv + toff[c], &dummy);
+    }
     if (threadIdx.x == 0) {
       cnt[c] = k;
       atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
@@ -847,14 +884,13 @@ __device__ __forceinline__ bool grow_better(const GrowBest& x, const GrowBest& y
 
 template <int BS>
 __device__ GrowBest block_grow_argmax(GrowBest b, GrowBest* sm) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  butterfly<64>([&](auto o) {
     GrowBest o2;
-    o2.a = __shfl_xor(b.a, o, 64);
-    o2.g = __shfl_xor(b.g, o, 64);
-    o2.v = __shfl_xor(b.v, o, 64);
+    o2.a = xor_lane<decltype(o)::value>(b.a);
+    o2.g = xor_lane<decltype(o)::value>(b.g);
+    o2.v = xor_lane<decltype(o)::value>(b.v);
     if (grow_better(o2, b)) b = o2;
-  }
+  });
   if (BS == 64) return b;
   if (lane_id() == 0) sm[threadIdx.x / 64] = b;
   __syncthreads();
@@ -1055,7 +1091,11 @@ __device__ void b_trial_global(LevelView lv, const int64_t* tot, int K, int t, i
 constexpr int kTrialBlock = 256;
 constexpr int kTrialLdsMax = 3072;
 
-__device__ __forceinline__ size_t trial_lds_bytes(int32_t n) { return (size_t)n * 19 + 16; }
+// gain, b (int64), xadj (int32, n + 1), side, adjacency, move flag (int8),
+// plus one dirty flag per thread of the block
+__host__ __device__ constexpr size_t trial_lds_bytes(int32_t n, int bs) {
+  return (size_t)n * 23 + 4 + (size_t)bs + 16;
+}
 
 // Refinement passes on an LDS-resident state (gain, balance weight, side,
 // move flag per vertex); gains are updated incrementally (see above).
@@ -1133,9 +1173,11 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
   const int32_t n = lv.n;
   int64_t* s_gain = (int64_t*)lds;
   int64_t* s_b = s_gain + n;
-  int8_t* s_part = (int8_t*)(s_b + n);
+  int32_t* s_xadj = (int32_t*)(s_b + n);
+  int8_t* s_part = (int8_t*)(s_xadj + n + 1);
   int8_t* s_adj = s_part + n;
   int8_t* s_mv = s_adj + n;
+  uint8_t* s_dirty = (uint8_t*)(s_mv + n);  // BS flags: thread's own vertices changed
   __shared__ int64_t sml[BS / 64];
   __shared__ GrowBest sgb[BS / 64];
   SelShared& sel = *selp;
@@ -1151,49 +1193,162 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     s_mv[v] = 0;
     W += bv;
   }
+  for (int32_t v = threadIdx.x; v <= n; v += BS) s_xadj[v] = lv.xadj[v];
+  s_dirty[threadIdx.x] = 0;
   W = block_sum<BS, int64_t>(W, sml);
   const int64_t tg = ctrl->tgt[gs], mg = ctrl->ref.maxw[gs];
   const int32_t seedv = (int32_t)(((int64_t)t * n) / K);
+  // Greedy growing of side gs, one vertex at a time.  Thread t owns the
+  // vertices v = t mod BS and keeps the best of those that can still be
+  // added; it rescans them only when one of them changed (the pick or a
+  // neighbour of it) or its best stopped fitting.  The room mg - pg only
+  // shrinks, so a vertex that does not fit never fits again, and a best that
+  // still fits stays the best of the owner's fitting vertices.
+  //
+  // Fast form: |gain(v)| <= tot(v), so when every tot is below 2^61 the pair
+  // (adjacent, gain) packs into one ordered 63-bit key (adjacent << 62) |
+  // (gain + 2^61), held in s_gain while growing, and the order (adjacent
+  // desc, gain desc, id asc) becomes one unsigned compare plus the id.
+  int64_t tmax = 0;
+  for (int32_t v = threadIdx.x; v < n; v += BS) tmax = tot[v] > tmax ? tot[v] : tmax;
+  tmax = block_max<BS, int64_t>(tmax, sml);
+  const bool packed = tmax < ((int64_t)1 << 61);
+  const uint64_t kBias = 1ull << 61, kAdj = 1ull << 62, kField = (1ull << 62) - 1;
   int64_t pg = 0;
-  bool first = true;
-  // greedy growing of side gs, one vertex at a time
-  while (pg < tg) {
-    int32_t pick = -1;
-    if (first && pg + s_b[seedv] <= mg) {
-      pick = seedv;
-    } else {
-      GrowBest best;
-      best.v = -1;
-      best.a = 0;
-      best.g = 0;
+  if (packed) {
+    uint64_t* s_key = (uint64_t*)s_gain;
+    for (int32_t v = threadIdx.x; v < n; v += BS) s_key[v] = (uint64_t)s_gain[v] + kBias;
+    __syncthreads();
+    // (key, id) of the best fitting vertex of this thread; key 0 = none
+    auto rescan = [&](int64_t room, uint64_t& bk, int32_t& bv) {
+      bk = 0;
+      bv = -1;
+      // a fixed, unrolled trip count: every load of the owner's vertices is
+      // in flight at once (slots past n read vertex 0 and are discarded)
+      constexpr int kPer = (kTrialLdsMax + BS - 1) / BS;
+#pragma unroll
+      for (int q = 0; q < kPer; q++) {
+        const int32_t v = (int32_t)threadIdx.x + q * BS;
+        const int32_t vv = v < n ? v : 0;
+        const uint64_t k = (v < n && s_part[vv] == gb && s_b[vv] <= room) ? s_key[vv] : 0;
+        const bool take = k > bk;  // ascending ids: ties keep the smaller id
+        bk = take ? k : bk;
+        bv = take ? v : bv;
+      }
+    };
+    auto better = [](uint64_t k2, int32_t v2, uint64_t k, int32_t v) {
+      return k2 > k || (k2 == k && v2 < v);
+    };
+    __shared__ uint64_t s_bk[BS / 64];
+    __shared__ int32_t s_bv[BS / 64];
+    uint64_t bk;
+    int32_t bv;
+    rescan(mg, bk, bv);
+    bool first = true;
+    while (pg < tg) {
+      uint64_t wk = bk;
+      int32_t wv = bv;
+      butterfly<64>([&](auto o) {
+        const uint64_t k2 = xor_lane<decltype(o)::value>(wk);
+        const int32_t v2 = xor_lane<decltype(o)::value>(wv);
+        const bool t2 = better(k2, v2, wk, wv);
+        wk = t2 ? k2 : wk;
+        wv = t2 ? v2 : wv;
+      });
+      if (lane_id() == 0) {
+        s_bk[threadIdx.x / 64] = wk;
+        s_bv[threadIdx.x / 64] = wv;
+      }
+      __syncthreads();
+      uint64_t gk = s_bk[0];
+      int32_t gv = s_bv[0];
+#pragma unroll
+      for (int w = 1; w < BS / 64; w++) {
+        const bool t2 = better(s_bk[w], s_bv[w], gk, gv);
+        gk = t2 ? s_bk[w] : gk;
+        gv = t2 ? s_bv[w] : gv;
+      }
+      int32_t pick = gk ? gv : -1;
+      if (first && pg + s_b[seedv] <= mg) pick = seedv;
+      first = false;
+      if (pick < 0) break;
+      if (threadIdx.x == 0) {
+        s_part[pick] = (int8_t)gs;
+        // gain -> -gain in the biased field; the adjacency bit is kept
+        const uint64_t k = s_key[pick];
+        s_key[pick] = (k & kAdj) | (uint64_t)(2 * (int64_t)kBias - (int64_t)(k & kField));
+        s_dirty[pick % BS] = 1;
+      }
+      __syncthreads();
+      const int32_t e1 = s_xadj[pick + 1];
+      for (int32_t e = s_xadj[pick] + threadIdx.x; e < e1; e += BS) {
+        const int32_t y = lv.adj[e];
+        const int64_t w = lv.w[e];
+        const uint64_t k = s_key[y] + (uint64_t)(s_part[y] == gs ? -2 * w : 2 * w);
+        s_key[y] = k | kAdj;
+        s_dirty[y % BS] = 1;
+      }
+      pg += s_b[pick];
+      __syncthreads();
+      const int64_t room = mg - pg;
+      if (s_dirty[threadIdx.x] || (bv >= 0 && s_b[bv] > room)) {
+        s_dirty[threadIdx.x] = 0;
+        rescan(room, bk, bv);
+      }
+    }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      const uint64_t k = s_key[v];
+      s_adj[v] = (int8_t)(k >> 62);
+      s_gain[v] = (int64_t)(k & kField) - (int64_t)kBias;
+    }
+  } else {
+    auto rescan = [&](int64_t room) {
+      GrowBest lb;
+      lb.v = -1;
+      lb.a = 0;
+      lb.g = 0;
       for (int32_t v = threadIdx.x; v < n; v += BS) {
-        if (s_part[v] != gb || pg + s_b[v] > mg) continue;
+        if (s_part[v] != gb || s_b[v] > room) continue;
         GrowBest x;
         x.a = s_adj[v];
         x.g = s_gain[v];
         x.v = v;
-        if (grow_better(x, best)) best = x;
+        if (grow_better(x, lb)) lb = x;
       }
-      best = block_grow_argmax<BS>(best, sgb);
-      pick = best.v;
+      return lb;
+    };
+    GrowBest lb = rescan(mg);
+    bool first = true;
+    while (pg < tg) {
+      const GrowBest best = block_grow_argmax<BS>(lb, sgb);
+      int32_t pick = best.v;
+      if (first && pg + s_b[seedv] <= mg) pick = seedv;
+      first = false;
+      if (pick < 0) break;
+      if (threadIdx.x == 0) {
+        s_part[pick] = (int8_t)gs;
+        s_gain[pick] = -s_gain[pick];
+        s_dirty[pick % BS] = 1;
+      }
+      __syncthreads();
+      // the neighbours of the pick are distinct (canonical rows): plain updates
+      const int32_t e1 = s_xadj[pick + 1];
+      for (int32_t e = s_xadj[pick] + threadIdx.x; e < e1; e += BS) {
+        const int32_t y = lv.adj[e];
+        const int64_t w = lv.w[e];
+        s_adj[y] = 1;
+        s_gain[y] += s_part[y] == gs ? -2 * w : 2 * w;
+        s_dirty[y % BS] = 1;
+      }
+      pg += s_b[pick];
+      __syncthreads();
+      const int64_t room = mg - pg;
+      if (s_dirty[threadIdx.x] || (lb.v >= 0 && s_b[lb.v] > room)) {
+        s_dirty[threadIdx.x] = 0;
+        lb = rescan(room);
+      }
     }
-    first = false;
-    if (pick < 0) break;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_part[pick] = (int8_t)gs;
-      s_gain[pick] = -s_gain[pick];
-    }
-    __syncthreads();
-    for (int32_t e = lv.xadj[pick] + threadIdx.x; e < lv.xadj[pick + 1]; e += BS) {
-      const int32_t y = lv.adj[e];
-      const int64_t w = lv.w[e];
-      s_adj[y] = 1;
-      atomicAdd((unsigned long long*)&s_gain[y],
-                (unsigned long long)(s_part[y] == gs ? -2 * w : 2 * w));
-    }
-    pg += s_b[pick];
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     srf.maxw[0] = ctrl->ref.maxw[0];
@@ -1203,7 +1358,9 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     start_level(&srf, npass);
   }
   __syncthreads();
-  lds_refine<BS>(lv, s_gain, s_b, s_part, s_mv, srf, sel);
+  LevelView lvl = lv;
+  lvl.xadj = s_xadj;
+  lds_refine<BS>(lvl, s_gain, s_b, s_part, s_mv, srf, sel);
   // cut = sum over v of (gain + tot) / 4
   int64_t q = 0;
   for (int32_t v = threadIdx.x; v < n; v += BS) q += s_gain[v] + tot[v];
@@ -1236,8 +1393,7 @@ __device__ __forceinline__ uint64_t sat62(uint64_t a, uint64_t b) {
 
 template <int BS>
 __device__ uint64_t block_sum_sat(uint64_t v, uint64_t* sm) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = sat62(v, __shfl_xor(v, o, 64));
+  butterfly<64>([&](auto o) { v = sat62(v, xor_lane<decltype(o)::value>(v)); });
   if (lane_id() == 0) sm[threadIdx.x / 64] = v;
   __syncthreads();
   uint64_t r = 0;
