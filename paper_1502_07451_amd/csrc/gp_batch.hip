@@ -455,7 +455,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.b = a.bal ? f.vg : f.vc;
     const int tw = team_width_dev(f.n, f.nnz);
     for (int p = 0; p < a.P; p++) {
-      TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, 0, 1)));
+      TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, nullptr, 0, 1)));
       __syncthreads();
       b_refine_apply(f.part, &ctrl->ref, sc.list, ws.pass_sink, 0, 1);
       __syncthreads();

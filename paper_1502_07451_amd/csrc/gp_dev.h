@@ -308,25 +308,37 @@ __device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int 
     for (int q = threadIdx.x; q < 256; q += BS) sh->hist[q] = 0;
     __syncthreads();
     const u128 P = sh->prefix;
-    // uniform trip count: every lane of a wave takes part in the ballots
-    for (uint32_t base = 0; base < cnt; base += BS) {
-      const uint32_t i = base + threadIdx.x;
-      Cand c;
-      c.b = 0;
-      int bkt = -1;
-      if (i < cnt && items.get(i, c)) {
-        const u128 k = cand_key(c, gmin, idbits);
-        if ((k >> (shf + 8)) == P) bkt = (int)((k >> shf) & 255);
+    // uniform trip count: every lane of a wave takes part in the ballots;
+    // U candidates per thread are loaded before any is used, so that the
+    // loads of one round overlap instead of paying a round trip each
+    constexpr int U = 4;
+    for (uint32_t base = 0; base < cnt; base += BS * U) {
+      Cand cs[U];
+      bool got[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const uint32_t i = base + (uint32_t)(u * BS) + threadIdx.x;
+        cs[u].b = 0;
+        got[u] = i < cnt && items.get(i, cs[u]);
       }
-      const uint64_t hits = __ballot(bkt >= 0);
-      if (hits == 0) continue;
-      const int lead = __builtin_ctzll(hits);
-      const int b0 = __shfl(bkt, lead, 64);
-      if (__ballot(bkt >= 0 && bkt != b0) == 0) {
-        const int64_t sum = team_sum<64, int64_t>(bkt >= 0 ? c.b : 0);
-        if (lane == lead) atomicAdd((unsigned long long*)&sh->hist[b0], (unsigned long long)sum);
-      } else if (bkt >= 0) {
-        atomicAdd((unsigned long long*)&sh->hist[bkt], (unsigned long long)c.b);
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        int bkt = -1;
+        if (got[u]) {
+          const u128 k = cand_key(cs[u], gmin, idbits);
+          if ((k >> (shf + 8)) == P) bkt = (int)((k >> shf) & 255);
+        }
+        const uint64_t hits = __ballot(bkt >= 0);
+        if (hits == 0) continue;
+        const int lead = __builtin_ctzll(hits);
+        const int b0 = __shfl(bkt, lead, 64);
+        if (__ballot(bkt >= 0 && bkt != b0) == 0) {
+          const int64_t sum = team_sum<64, int64_t>(bkt >= 0 ? cs[u].b : 0);
+          if (lane == lead)
+            atomicAdd((unsigned long long*)&sh->hist[b0], (unsigned long long)sum);
+        } else if (bkt >= 0) {
+          atomicAdd((unsigned long long*)&sh->hist[bkt], (unsigned long long)cs[u].b);
+        }
       }
     }
     __syncthreads();

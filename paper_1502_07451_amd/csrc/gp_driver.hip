@@ -569,7 +569,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     const LevelView fv = f->view(bal);
     for (int p = 0; p < P; p++) {
       g->prof.idx = p;
-      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, tw,
+      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.toff, tw,
                               &g->ctrl->lvl_pass[l], s));
     }
     if ((st = record(l, false)) != GP_OK) return st;

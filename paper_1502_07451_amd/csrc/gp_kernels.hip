@@ -124,9 +124,10 @@ __global__ __launch_bounds__(kBlock) void k_contract_compact(const Ctrl* ctrl,
 
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_refine_gain(LevelView lv, const int8_t* part,
-                                                        RefCtl* rc, Cand* list) {
+                                                        RefCtl* rc, Cand* list,
+                                                        int64_t* partials) {
   __shared__ SelShared sel;
-  b_refine_gain<TW>(lv, part, rc, list, &sel, (int)blockIdx.x, (int)gridDim.x);
+  b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_apply(int8_t* part, RefCtl* rc,
@@ -227,7 +228,7 @@ const char* const kProfNames[PK_N] = {
     "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_compact", "k_init_tot",
     "k_init_trials", "k_refine_gain", "k_refine_apply", "k_project", "k_final_stats"};
 
-Prof* g_prof = nullptr;
+thread_local Prof* g_prof = nullptr;
 
 static hipEvent_t prof_event(Prof* p) {
   if (p->used >= p->npool) {
@@ -425,23 +426,24 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
 
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
-                    hipStream_t s) {
+                    int64_t* partials, hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * TW, kBlock * 2);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
-  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list);
+  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
   KCHECK();
   return true;
 }
 
-bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list, int tw,
+bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                        int64_t* partials, int tw,
                         int32_t* pass_out, hipStream_t s) {
   bool ok;
   switch (tw) {
-    case 4: ok = gain_tw<4>(lv, part, rc, list, s); break;
-    case 8: ok = gain_tw<8>(lv, part, rc, list, s); break;
-    case 16: ok = gain_tw<16>(lv, part, rc, list, s); break;
-    case 32: ok = gain_tw<32>(lv, part, rc, list, s); break;
-    default: ok = gain_tw<64>(lv, part, rc, list, s); break;
+    case 4: ok = gain_tw<4>(lv, part, rc, list, partials, s); break;
+    case 8: ok = gain_tw<8>(lv, part, rc, list, partials, s); break;
+    case 16: ok = gain_tw<16>(lv, part, rc, list, partials, s); break;
+    case 32: ok = gain_tw<32>(lv, part, rc, list, partials, s); break;
+    default: ok = gain_tw<64>(lv, part, rc, list, partials, s); break;
   }
   if (!ok) return false;
   {
@@ -493,14 +495,12 @@ bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, cons
   ProfScope ps(PK_INIT_TRIALS, 0, 0.0, s);
   if (lv.n <= kTrialLdsMax) {
     const size_t dyn = trial_lds_bytes(lv.n, kTrialBlock);
-    static bool lds_attr = false;  // more than 64 KB of dynamic LDS must be allowed once
-    if (!lds_attr) {
-      if (hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)trial_lds_bytes(kTrialLdsMax, kTrialBlock)) != hipSuccess)
-        return false;
-      lds_attr = true;
-    }
+    // more than 64 KB of dynamic LDS must be allowed once (thread-safe static)
+    static const bool lds_attr =
+        hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)trial_lds_bytes(kTrialLdsMax, kTrialBlock)) == hipSuccess;
+    if (!lds_attr) return false;
     k_init_trials_lds<kTrialBlock><<<K, kTrialBlock, dyn, s>>>(lv, is.tot, K, gs, npass, ctrl,
                                                                is.ctl, is.part, is.res, out_part);
     KCHECK();

@@ -57,7 +57,7 @@ struct Prof {
   int level = 0, idx = 0;
   bool failed = false;
 };
-extern Prof* g_prof;   // set by the driver around a profiled call (one host thread)
+extern thread_local Prof* g_prof;  // set by the driver around a profiled call, per host thread
 
 // records events around one launch when profiling is on
 struct ProfScope {
@@ -78,7 +78,9 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
 bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, const Scratch& sc,
                        int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
                        hipStream_t s);
-bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list, int tw,
+// partials: 4 int64 per block of the gain kernel (at least n / 32 entries)
+bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                        int64_t* partials, int tw,
                         int32_t* pass_out, hipStream_t s);
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
                     int npass, hipStream_t s);

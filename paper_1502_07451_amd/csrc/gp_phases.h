@@ -690,7 +690,7 @@ __device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_b, int64_t
 template <int TW>
 __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list, SelShared* sel,
-                                                        int bid_, int nblk_) {
+                                                        int64_t* partials, int bid_, int nblk_) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   int mode, s;
@@ -739,21 +739,43 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
   cb = block_sum<kBlock, int64_t>(cb, sml);
   gmn = block_min<kBlock, int64_t>(gmn, sml);
   gmx = block_max<kBlock, int64_t>(gmx, sml);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&rc->ext_sum, (unsigned long long)ext_acc);
-    atomicAdd((unsigned long long*)&rc->cand_b, (unsigned long long)cb);
-    atomicMin((long long*)&rc->gmin_acc, (long long)gmn);
-    atomicMax((long long*)&rc->gmax_acc, (long long)gmx);
+  if (nblk_ > 1) {
+    // per-block partials (4 x nblk int64) instead of atomics on four shared
+    // words, which serialise in L2 when hundreds of blocks finish together
+    if (threadIdx.x == 0) {
+      partials[4 * bid_ + 0] = ext_acc;
+      partials[4 * bid_ + 1] = cb;
+      partials[4 * bid_ + 2] = gmn;
+      partials[4 * bid_ + 3] = gmx;
+    }
+    if (!last_block(&rc->ctr_gain, (uint32_t)nblk_)) return;
+    ext_acc = 0;
+    cb = 0;
+    gmn = INT64_MAX;
+    gmx = INT64_MIN;
+    for (int i = threadIdx.x; i < nblk_; i += kBlock) {
+      ext_acc += partials[4 * i + 0];
+      cb += partials[4 * i + 1];
+      gmn = partials[4 * i + 2] < gmn ? partials[4 * i + 2] : gmn;
+      gmx = partials[4 * i + 3] > gmx ? partials[4 * i + 3] : gmx;
+    }
+    ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+    cb = block_sum<kBlock, int64_t>(cb, sml);
+    gmn = block_min<kBlock, int64_t>(gmn, sml);
+    gmx = block_max<kBlock, int64_t>(gmx, sml);
   }
-  if (!tail_gate(&rc->ctr_gain, nblk_)) return;
   if (threadIdx.x == 0) {
+    rc->ext_sum = ext_acc;
+    rc->cand_b = cb;
+    rc->gmin_acc = gmn;
+    rc->gmax_acc = gmx;
     rc->mode = mode;
     rc->s = s;
   }
   __syncthreads();
-  const ListItems items{list, rc->ncand};
-  decide_admission<kBlock>(rc, items, rc->ncand, rc->cand_b, rc->gmin_acc, rc->gmax_acc, lv.n,
-                           sel);
+  const uint32_t ncand = rc->ncand;
+  const ListItems items{list, ncand};
+  decide_admission<kBlock>(rc, items, ncand, cb, gmn, gmx, lv.n, sel);
 }
 
 __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,

@@ -285,3 +285,31 @@ def test_layered4m_full_size(gp):
     assert res.cut == int(exp["cut"]) and res.levels == int(exp["levels"])
     assert (res.load[0], res.load[1]) == (int(exp["load0"]), int(exp["load1"]))
     assert (res.time[0], res.time[1]) == (int(exp["time0"]), int(exp["time1"]))
+
+
+def test_concurrent_streams_match_serial(gp):
+    """Two graphs partitioned at the same time from two host threads, each on
+    its own stream, give the oracle's results (as the benchmark step runs)."""
+    import concurrent.futures
+    import ctypes
+
+    import torch
+    graphs = dagen.config_cholesky64_lu48()
+    refs = [oracle.partition(g, oracle.Options(ratio=(1, 4), eps_ppm=30000)) for g in graphs]
+    streams = [torch.cuda.Stream() for _ in graphs]
+    arrays = [gp.to_device(g) for g in graphs]
+    torch.cuda.synchronize()
+    hs = [gp.Graph(*a, stream=ctypes.c_void_p(s.cuda_stream)) for a, s in zip(arrays, streams)]
+    parts = [torch.empty(g.n, dtype=torch.int8, device="cuda") for g in graphs]
+    torch.cuda.synchronize()
+    o = gp.options(ratio=(1, 4), eps_ppm=30000)
+    say("case concurrent streams")
+    with concurrent.futures.ThreadPoolExecutor(2) as ex:
+        for rep in range(3):
+            res = list(ex.map(lambda i: hs[i].partition(o, part=parts[i])[1], range(2)))
+            torch.cuda.synchronize()
+            for p, r, ref in zip(parts, res, refs):
+                assert np.array_equal(p.cpu().numpy(), ref.part), f"repeat {rep}"
+                assert r.cut == ref.cut and (r.load[0], r.load[1]) == ref.load
+    for h in hs:
+        h.close()
