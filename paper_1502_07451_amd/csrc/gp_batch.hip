@@ -143,6 +143,7 @@ __device__ WgScratch wg_scratch(const BatchArgs& a) {
   s.sc.tmpv = (int64_t*)(base + off[11]);
   s.sc.longlist = (int32_t*)(base + off[12]);
   s.sc.list = (Cand*)(base + off[13]);
+  s.sc.partials = nullptr;  // one workgroup per graph: no cross-block partials
   s.tot = (int64_t*)(base + off[14]);
   s.tctl = (RefCtl*)(base + off[15]);
   s.tpart = (int8_t*)(base + off[16]);

@@ -93,6 +93,7 @@ struct gp_graph {
   // level scratch
   DBuf<int32_t> prop, tile_lead, cmem0, cmem1, cnt, tmpk, longlist;
   DBuf<int64_t> tile_ub, toff, tile_cnt, tmpv;
+  DBuf<int64_t> partials;  // 4 per block of a multi-block reduction (grids of <= 4096)
   DBuf<Cand> list;
   // initial bisection scratch
   DBuf<int64_t> i_tot, i_conn, i_res;
@@ -125,6 +126,7 @@ struct gp_graph {
     s.tmpv = tmpv.p;
     s.longlist = longlist.p;
     s.list = list.p;
+    s.partials = partials.p;
     return s;
   }
   bool ensure_scratch() {
@@ -132,7 +134,8 @@ struct gp_graph {
     return prop.ensure(n1) && tile_lead.ensure(n1 / kTileV + 2) &&
            tile_ub.ensure(n1 / kTileV + 2) && cmem0.ensure(n1) && cmem1.ensure(n1) &&
            toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
-           tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1);
+           tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1) &&
+           partials.ensure(4 * 4096);
   }
   bool ensure_init(int32_t nl, int K) {
     const int64_t kn = (int64_t)K * (nl > 0 ? nl : 1);
@@ -157,7 +160,7 @@ struct gp_graph {
     }
     prop.release(); tile_lead.release(); cmem0.release(); cmem1.release(); cnt.release();
     tmpk.release(); longlist.release(); tile_ub.release(); toff.release(); tile_cnt.release();
-    tmpv.release(); list.release();
+    tmpv.release(); list.release(); partials.release();
     i_tot.release(); i_conn.release(); i_res.release(); i_ctl.release(); i_part.release();
     i_adjc.release(); i_list.release();
     m_ha.release(); m_hb.release(); m_inv.release(); m_score.release(); m_order.release();
@@ -569,7 +572,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     const LevelView fv = f->view(bal);
     for (int p = 0; p < P; p++) {
       g->prof.idx = p;
-      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.toff, tw,
+      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
                               &g->ctrl->lvl_pass[l], s));
     }
     if ((st = record(l, false)) != GP_OK) return st;

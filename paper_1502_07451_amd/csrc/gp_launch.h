@@ -19,6 +19,7 @@ struct Scratch {
   int64_t* tmpv;       // nnz
   int32_t* longlist;   // n
   Cand* list;          // n
+  int64_t* partials;   // 4 x 4096: per-block partial results of a reduction
 };
 
 // scratch of the initial bisection, sized for the coarsest graph and K trials
@@ -78,7 +79,7 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
 bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, const Scratch& sc,
                        int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
                        hipStream_t s);
-// partials: 4 int64 per block of the gain kernel (at least n / 32 entries)
+// partials: 4 int64 per block of the gain kernel (grids are capped at 4096)
 bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
                         int64_t* partials, int tw,
                         int32_t* pass_out, hipStream_t s);

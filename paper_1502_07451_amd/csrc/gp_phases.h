@@ -1236,27 +1236,36 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
   tmax = block_max<BS, int64_t>(tmax, sml);
   const bool packed = tmax < ((int64_t)1 << 61);
   const uint64_t kBias = 1ull << 61, kAdj = 1ull << 62, kField = (1ull << 62) - 1;
+  const uint64_t kSide = 1ull << 63;
   int64_t pg = 0;
   if (packed) {
     uint64_t* s_key = (uint64_t*)s_gain;
     for (int32_t v = threadIdx.x; v < n; v += BS) s_key[v] = (uint64_t)s_gain[v] + kBias;
     __syncthreads();
-    // (key, id) of the best fitting vertex of this thread; key 0 = none
-    auto rescan = [&](int64_t room, uint64_t& bk, int32_t& bv) {
+    // (key, id) of the best fitting vertex of this thread; key 0 = none.
+    // Bit 63 of a key marks a vertex already on side gs.  The slot count is
+    // fixed per size class so that the loads of all slots are in flight at
+    // once (slots past n read vertex 0 and are discarded).
+    auto rescan_slots = [&](auto slots, int64_t room, uint64_t& bk, int32_t& bv) {
+      constexpr int S = decltype(slots)::value;
       bk = 0;
       bv = -1;
-      // a fixed, unrolled trip count: every load of the owner's vertices is
-      // in flight at once (slots past n read vertex 0 and are discarded)
-      constexpr int kPer = (kTrialLdsMax + BS - 1) / BS;
 #pragma unroll
-      for (int q = 0; q < kPer; q++) {
+      for (int q = 0; q < S; q++) {
         const int32_t v = (int32_t)threadIdx.x + q * BS;
         const int32_t vv = v < n ? v : 0;
-        const uint64_t k = (v < n && s_part[vv] == gb && s_b[vv] <= room) ? s_key[vv] : 0;
+        const uint64_t kv = s_key[vv];
+        const uint64_t k = (v < n && (kv >> 63) == 0 && s_b[vv] <= room) ? kv : 0;
         const bool take = k > bk;  // ascending ids: ties keep the smaller id
         bk = take ? k : bk;
         bv = take ? v : bv;
       }
+    };
+    static_assert(kTrialLdsMax <= 12 * BS, "slot classes cover the LDS-resident sizes");
+    auto rescan = [&](int64_t room, uint64_t& bk, int32_t& bv) {
+      if (n <= 4 * BS) rescan_slots(LaneXor<4>{}, room, bk, bv);
+      else if (n <= 8 * BS) rescan_slots(LaneXor<8>{}, room, bk, bv);
+      else rescan_slots(LaneXor<12>{}, room, bk, bv);
     };
     auto better = [](uint64_t k2, int32_t v2, uint64_t k, int32_t v) {
       return k2 > k || (k2 == k && v2 < v);
@@ -1296,9 +1305,11 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
       if (pick < 0) break;
       if (threadIdx.x == 0) {
         s_part[pick] = (int8_t)gs;
-        // gain -> -gain in the biased field; the adjacency bit is kept
+        // gain -> -gain in the biased field; the adjacency bit is kept and
+        // bit 63 marks the side
         const uint64_t k = s_key[pick];
-        s_key[pick] = (k & kAdj) | (uint64_t)(2 * (int64_t)kBias - (int64_t)(k & kField));
+        s_key[pick] = kSide | (k & kAdj) |
+                      (uint64_t)(2 * (int64_t)kBias - (int64_t)(k & kField));
         s_dirty[pick % BS] = 1;
       }
       __syncthreads();
@@ -1306,8 +1317,8 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
       for (int32_t e = s_xadj[pick] + threadIdx.x; e < e1; e += BS) {
         const int32_t y = lv.adj[e];
         const int64_t w = lv.w[e];
-        const uint64_t k = s_key[y] + (uint64_t)(s_part[y] == gs ? -2 * w : 2 * w);
-        s_key[y] = k | kAdj;
+        const uint64_t ky = s_key[y];
+        s_key[y] = (ky + (uint64_t)((ky >> 63) ? -2 * w : 2 * w)) | kAdj;
         s_dirty[y % BS] = 1;
       }
       pg += s_b[pick];
@@ -1321,7 +1332,7 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     __syncthreads();
     for (int32_t v = threadIdx.x; v < n; v += BS) {
       const uint64_t k = s_key[v];
-      s_adj[v] = (int8_t)(k >> 62);
+      s_adj[v] = (int8_t)((k >> 62) & 1);
       s_gain[v] = (int64_t)(k & kField) - (int64_t)kBias;
     }
   } else {
