@@ -41,6 +41,27 @@ def ensure_built():
         __graft_entry__.build()
 
 
+KERNEL_SOURCES = ("gp_dev.h", "gp_internal.h", "gp_kernels.hip", "gp_phases.h")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or the kernel sources have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_cholesky64_lu48_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l)
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1502_07451_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != h.hexdigest():
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def aggregate(rows_lists):
     agg = {}
     for rows in rows_lists:
@@ -61,6 +82,9 @@ def main():
                     help="skip the 4M-vertex layered DAG and the 4,096-graph batch")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only warmup + timed steps (for profiler runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run 3 device copies of MIB MiB (the reference kernel that "
+                         "scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -115,6 +139,14 @@ def main():
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     value = edges / (ms_per_step / 1e3)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {args.copy_probe} MiB")
+        del src, dst
     if args.kernels_only:
         log(f"{args.steps} steps, {ms_per_step:.3f} ms/step, {value:.4g} edges/s")
         return
@@ -141,13 +173,7 @@ def main():
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        with open(tpath) as f:
-            tr = json.load(f)
-        if tr.get("kernel") == dom_name and tr.get("workload") == "cholesky64+lu48":
-            traffic = tr.get("bytes_per_launch")
+    traffic = measured_traffic(dom_name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": dom_name, "avg_launch_us": round(avg_ms * 1e3, 3),

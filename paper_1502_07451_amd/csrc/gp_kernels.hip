@@ -492,7 +492,11 @@ bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, cons
     k_init_tot<<<grid_for(lv.n, kBlock), kBlock, 0, s>>>(lv, is.tot);
   }
   KCHECK();
-  ProfScope ps(PK_INIT_TRIALS, 0, 0.0, s);
+  // each of the K trials reads the coarsest graph once (xadj, adj + w, b,
+  // incident sums) and writes its assignment
+  const double trial_bytes =
+      (double)K * (4.0 * (lv.n + 1) + 12.0 * lv.nnz + 16.0 * lv.n + 1.0 * lv.n);
+  ProfScope ps(PK_INIT_TRIALS, 0, lv.n <= kTrialLdsMax ? trial_bytes : 0.0, s);
   if (lv.n <= kTrialLdsMax) {
     const size_t dyn = trial_lds_bytes(lv.n, kTrialBlock);
     // more than 64 KB of dynamic LDS must be allowed once (thread-safe static)
