@@ -161,7 +161,7 @@ def export_coarsest(bb, opts, device, batch_ctx=None):
     return out
 
 
-def build_training_set(n_graphs: int, opts=None, lo: float = 2000.0, hi: float = 40000.0,
+def build_training_set(n_graphs: int, opts=None, lo: float = 300.0, hi: float = 8000.0,
                        seed: int = 1, per_batch: int = 4096, device="cuda", workers: int = 8,
                        pool=None) -> TrainSet:
     """Generates n_graphs DAGs (even: tiled Cholesky, odd: random layered,
@@ -285,8 +285,8 @@ def gain_test(bf16: np.ndarray, graphs, opts_kw: dict, device="cuda", reps: int 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--graphs", type=int, default=100000)
-    ap.add_argument("--lo", type=float, default=2000.0)
-    ap.add_argument("--hi", type=float, default=40000.0)
+    ap.add_argument("--lo", type=float, default=300.0)
+    ap.add_argument("--hi", type=float, default=8000.0)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--graphs-per-step", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)

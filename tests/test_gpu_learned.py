@@ -71,3 +71,25 @@ def test_learned_requires_model(gp):
         h.partition(gp.options(flags=gp.LEARNED))
     assert e.value.status == gp.EMODEL
     h.close()
+
+
+def test_trained_weights_match_oracle(gp):
+    """The committed trained weights: the learned path on the tiled Cholesky
+    T=64 DAG equals the oracle's, judge decision included."""
+    import os
+    from paper_1502_07451_amd import learn
+    if not os.path.exists(learn.WEIGHTS_PATH):
+        pytest.skip("no trained weights")
+    P = learn.load_weights()
+    g = dagen.config_cholesky64_lu48()[0]
+    say("case trained weights cholesky64")
+    ref = oracle.partition(g, oracle.Options(ratio=(1, 4), eps_ppm=30000,
+                                             flags=oracle.FLAG_LEARNED), model=P)
+    model = gp.Model(P)
+    h = gp.create(g)
+    part, res = h.partition(gp.options(ratio=(1, 4), eps_ppm=30000, flags=gp.LEARNED,
+                                       model=model.handle))
+    h.close()
+    model.close()
+    assert ref.status == 0 and res.used_learned == ref.used_learned
+    assert np.array_equal(part.cpu().numpy(), ref.part) and res.cut == ref.cut
