@@ -82,6 +82,8 @@ def main():
                     help="skip the 4M-vertex layered DAG and the 4,096-graph batch")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only warmup + timed steps (for profiler runs)")
+    ap.add_argument("--layered4m-kernels", action="store_true",
+                    help="only two partitions of the 4M-vertex layered DAG (for counter runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run 3 device copies of MIB MiB (the reference kernel that "
                          "scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -101,6 +103,26 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.layered4m_kernels:
+        g4 = dagen.config_layered4m()
+        h4 = gp.create(g4, dev)
+        p4 = torch.empty(g4.n, dtype=torch.int8, device=dev)
+        o4 = gp.options(ratio=(1, 3), eps_ppm=50000)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r4 = h4.partition(o4, part=p4)
+            torch.cuda.synchronize()
+            log(f"layered4m partition: {(time.perf_counter() - t0) * 1e3:.3f} ms, cut {r4.cut}")
+        if args.copy_probe > 0:
+            src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"copy probe: 3 copies of {args.copy_probe} MiB")
+        h4.close()
+        return
     graphs = dagen.config_cholesky64_lu48()
     edges = sum(g.m for g in graphs)
     dev_arrays = [gp.to_device(g, dev) for g in graphs]
@@ -196,6 +218,25 @@ def main():
            "create_ms": round(create_ms, 3),
            "roofline": roofline}
 
+    # secondary: end to end from host memory (gp_create over PCIe, partition,
+    # assignment back to the host), one DAG after the other
+    if not args.no_extra:
+        e2e = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for g in graphs:
+                hh = gp.Graph(g.n, np.ascontiguousarray(g.xadj, np.int32),
+                              np.ascontiguousarray(g.adjncy, np.int32),
+                              np.ascontiguousarray(g.adjwgt, np.int64),
+                              np.ascontiguousarray(g.vwgt, np.int64).reshape(-1))
+                hp = np.empty(g.n, np.int8)
+                hh.partition(opts, part=hp)
+                hh.close()
+            e2e.append(time.perf_counter() - t0)
+        te = statistics.median(e2e)
+        out["host_end_to_end"] = {"ms": round(te * 1e3, 3), "edges_per_s": round(edges / te, 1),
+                                  "note": "host arrays in, host assignment out, serial"}
+
     # larger single-graph case: the 4M-vertex layered DAG
     if not args.no_extra:
         g4 = dagen.config_layered4m()
@@ -211,6 +252,14 @@ def main():
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         t4 = statistics.median(times)
+        # algorithmic bytes of the pipeline at one matching round and one
+        # refinement pass per level: per level S = 4(n+1) + 12*2m + 16n read by
+        # matching, contraction and refinement, the next level written once,
+        # plus match, cmap and part (10 B per vertex)
+        _, _, tr4 = h4.partition(o4, part=p4, trace_cap=64)
+        S = [4 * (int(r[0]) + 1) + 12 * int(r[1]) + 16 * int(r[0]) for r in tr4]
+        b_alg = sum(3 * S[l] + (S[l + 1] if l + 1 < len(S) else 0) + 10 * int(tr4[l][0])
+                    for l in range(len(S) - 1))
         exp = {}
         gpath = os.path.join(ROOT, "tests", "golden", "layered4m_1to3_eps5.txt")
         with open(gpath) as f:
@@ -220,7 +269,9 @@ def main():
                             "edges_per_s": round(g4.m / t4, 1), "cut": r4.cut,
                             "levels": r4.levels,
                             "matches_oracle_digest": digest == exp.get("part_sha256")
-                            and r4.cut == int(exp.get("cut", -1))}
+                            and r4.cut == int(exp.get("cut", -1)),
+                            "alg_bytes": b_alg,
+                            "alg_bytes_frac_of_hbm_peak": round(b_alg / t4 / 1e9 / HBM_PEAK_GBS, 5)}
         h4.close()
         del p4
 
@@ -228,7 +279,6 @@ def main():
     if not args.no_extra:
         graphs_b = dagen.batch(4096, 100, 50000, 0)
         bb = dagen.concat(graphs_b)
-        del graphs_b
         dev_b = gp.batch_to_device(bb, dev)
         pb = torch.empty(int(bb.voff[-1]), dtype=torch.int8, device=dev)
         bt = gp.Batch()
@@ -254,6 +304,20 @@ def main():
                                           "tuning_ms_per_call": round(tune_ms, 3)}}
         bt.close()
         del dev_b, pb
+        if not args.no_cpu:
+            # the serial oracle over the same 4,096 graphs, one graph per host
+            # thread (the graphs are independent; ctypes releases the GIL)
+            import oracle
+            nthr = min(os.cpu_count() or 1, 16)
+            oo_b = oracle.Options(ratio=(1, 4), eps_ppm=30000)
+            t0 = time.perf_counter()
+            with concurrent.futures.ThreadPoolExecutor(nthr) as ex:
+                cuts = list(ex.map(lambda g: oracle.partition(g, oo_b).cut, graphs_b))
+            tcb = time.perf_counter() - t0
+            out["batch4096"]["cpu_oracle_threads"] = {
+                "threads": nthr, "ms": round(tcb * 1e3, 1), "edges_per_s": round(mb / tcb, 1),
+                "cut_sum_equal": int(sum(cuts)) == out["batch4096"]["cut_sum"]}
+        del graphs_b
 
     # learned coarsest-level proposal vs the plain bisection on the step's DAGs
     wpath = os.path.join(ROOT, "paper_1502_07451_amd", "mpnn_weights.bin")
@@ -278,10 +342,18 @@ def main():
         for g, r, gpart, gres in zip(graphs, refs, got, results):
             parity &= bool(np.array_equal(gpart, r.part)) and gres.cut == r.cut
         tc = statistics.median(t_cpu)
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f
+                                  if l.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": round(edges / tc, 1), "unit": "edges/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"the whole step (both DAGs), {reps} repetitions, "
-                                         f"median {tc * 1e3:.1f} ms, single-threaded"}
+                                         f"median {tc * 1e3:.1f} ms, single-threaded",
+                               "cpu_model": cpu_model, "nproc": os.cpu_count()}
         out["parity_with_oracle"] = parity
     for h in handles:
         h.close()

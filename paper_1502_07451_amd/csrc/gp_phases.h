@@ -1238,7 +1238,121 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
   const uint64_t kBias = 1ull << 61, kAdj = 1ull << 62, kField = (1ull << 62) - 1;
   const uint64_t kSide = 1ull << 63;
   int64_t pg = 0;
-  if (packed) {
+  // Compact form (incident weights below 2^49, at most 4,096 vertices): the
+  // whole order fits one 63-bit key, (adjacent << 62) | ((gain + 2^49) << 12)
+  // | (4095 - id), so the best is a plain unsigned maximum.  While a vertex of
+  // side gb is not picked its key only grows (a picked neighbour adds 2w to
+  // its gain and sets the adjacency bit), so each update is offered to the
+  // owner's best with an LDS atomicMax, and an owner rescans only when its
+  // best was picked or stopped fitting.
+  const bool compact = tmax < ((int64_t)1 << 49) && n <= 4096;
+  if (compact) {
+    uint64_t* s_key = (uint64_t*)s_gain;
+    __shared__ uint64_t s_best[BS];
+    __shared__ uint64_t s_wmax[BS / 64];
+    const uint64_t cBias = 1ull << 49, cAdj = 1ull << 62, cSide = 1ull << 63;
+    const uint64_t cField = ((1ull << 50) - 1) << 12;
+    for (int32_t v = threadIdx.x; v < n; v += BS)
+      s_key[v] = ((uint64_t)(s_gain[v] + (int64_t)cBias) << 12) | (uint64_t)(4095 - v);
+    __syncthreads();
+    auto vid = [](uint64_t k) { return (int32_t)(4095 - (int32_t)(k & 4095)); };
+    auto rescan_slots = [&](auto slots, int64_t room) {
+      constexpr int S = decltype(slots)::value;
+      uint64_t bk = 0;
+#pragma unroll
+      for (int q = 0; q < S; q++) {
+        const int32_t v = (int32_t)threadIdx.x + q * BS;
+        const int32_t vv = v < n ? v : 0;
+        const uint64_t kv = s_key[vv];
+        const uint64_t k = (v < n && (kv >> 63) == 0 && s_b[vv] <= room) ? kv : 0;
+        bk = k > bk ? k : bk;
+      }
+      return bk;
+    };
+    static_assert(kTrialLdsMax <= 12 * BS, "slot classes cover the LDS-resident sizes");
+    auto rescan = [&](int64_t room) {
+      if (n <= 4 * BS) return rescan_slots(LaneXor<4>{}, room);
+      if (n <= 8 * BS) return rescan_slots(LaneXor<8>{}, room);
+      return rescan_slots(LaneXor<12>{}, room);
+    };
+    s_best[threadIdx.x] = rescan(mg);
+    __syncthreads();
+    bool first = true;
+    int32_t last_pick = -1;
+    uint64_t seen = 0;     // the owner's best as of its last check
+    int64_t seen_b = 0;    // and that vertex's balance weight
+    while (pg < tg) {
+      const int64_t room = mg - pg;
+      uint64_t bk = s_best[threadIdx.x];
+      if (bk != 0) {
+        // only the last pick changed side; only the best's weight can stop
+        // fitting, and it is reloaded only when the best changed
+        const int32_t bv = vid(bk);
+        if (bk != seen) {
+          seen = bk;
+          seen_b = s_b[bv];
+        }
+        if (bv == last_pick || seen_b > room) {
+          bk = rescan(room);
+          s_best[threadIdx.x] = bk;
+          seen = bk;
+          seen_b = bk ? s_b[vid(bk)] : 0;
+        }
+      }
+      uint64_t wk = bk;
+      butterfly<64>([&](auto o) {
+        const uint64_t k2 = xor_lane<decltype(o)::value>(wk);
+        wk = k2 > wk ? k2 : wk;
+      });
+      if (lane_id() == 0) s_wmax[threadIdx.x / 64] = wk;
+      __syncthreads();
+      uint64_t gk = s_wmax[0];
+#pragma unroll
+      for (int w = 1; w < BS / 64; w++) gk = s_wmax[w] > gk ? s_wmax[w] : gk;
+      int32_t pick = gk ? vid(gk) : -1;
+      if (first && pg + s_b[seedv] <= mg) pick = seedv;
+      first = false;
+      if (pick < 0) break;
+      last_pick = pick;
+      // the first slice of the pick's row is fetched before the barrier, so
+      // its global latency overlaps the side update below
+      const int32_t e0 = s_xadj[pick], e1 = s_xadj[pick + 1];
+      const int32_t ef = e0 + (int32_t)threadIdx.x;
+      int32_t y0 = 0;
+      int64_t w0 = 0;
+      if (ef < e1) {
+        y0 = lv.adj[ef];
+        w0 = lv.w[ef];
+      }
+      const int64_t bp = s_b[pick];
+      if (threadIdx.x == 0) {
+        s_part[pick] = (int8_t)gs;
+        const uint64_t k = s_key[pick];
+        const int64_t f = (int64_t)((k & cField) >> 12);  // gain + 2^49
+        s_key[pick] = cSide | (k & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
+                      (k & 4095);
+      }
+      __syncthreads();
+      const int64_t room_next = room - bp;
+      for (int32_t e = ef; e < e1; e += BS) {
+        const int32_t y = e == ef ? y0 : lv.adj[e];
+        const int64_t w = e == ef ? w0 : lv.w[e];
+        const uint64_t ky = s_key[y];
+        const bool side = (ky >> 63) != 0;
+        const uint64_t nk = (ky + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
+        s_key[y] = nk;
+        if (!side && s_b[y] <= room_next) atomicMax((unsigned long long*)&s_best[y % BS], nk);
+      }
+      pg += bp;
+      __syncthreads();
+    }
+    __syncthreads();
+    for (int32_t v = threadIdx.x; v < n; v += BS) {
+      const uint64_t k = s_key[v];
+      s_adj[v] = (int8_t)((k >> 62) & 1);
+      s_gain[v] = (int64_t)((k & cField) >> 12) - (int64_t)cBias;
+    }
+  } else if (packed) {
     uint64_t* s_key = (uint64_t*)s_gain;
     for (int32_t v = threadIdx.x; v < n; v += BS) s_key[v] = (uint64_t)s_gain[v] + kBias;
     __syncthreads();
