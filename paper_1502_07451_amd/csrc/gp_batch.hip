@@ -345,7 +345,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
                     sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1);
     __syncthreads();
     b_contract_long(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                    sc.tile_cnt, sc.longlist, ntc, lds, 0, 1);
+                    sc.tile_cnt, sc.longlist, ntc, lds, false, 0, 1);
     __syncthreads();
     b_contract_compact(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv, cxadj, cadj, cw, ntc,
                        0, 1);

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_contract_long(LevelView lv, const in
                                                           int ntiles_c) {
   extern __shared__ __align__(16) unsigned char dyn_long[];
   b_contract_long(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist,
-                  ntiles_c, dyn_long, (int)blockIdx.x, (int)gridDim.x);
+                  ntiles_c, dyn_long, true, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_contract_compact(const Ctrl* ctrl,
@@ -405,7 +405,12 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
                                          sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1);
   }
   KCHECK();
-  const size_t dyn = (size_t)kWin * (sizeof(int64_t) + sizeof(int32_t));
+  // the dense window plus a staged copy of one row (96 KB)
+  const size_t dyn = (size_t)(kWin + kSortCap) * (sizeof(int64_t) + sizeof(int32_t));
+  static const bool long_attr =
+      hipFuncSetAttribute((const void*)k_contract_long, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)dyn) == hipSuccess;
+  if (!long_attr) return false;
   {
     ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
     // rows of more than kWaveCap candidates: one block each (a level of a large
@@ -427,7 +432,9 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
                     int64_t* partials, hipStream_t s) {
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock * 8);
+  // a few rows per team amortise the block-completion tail; full-wave teams
+  // (long rows) keep one or two rows each so that the row loads stay in flight
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock * (TW == 64 ? 2 : 8));
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
   k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
   KCHECK();

@@ -400,6 +400,16 @@ struct CoarseRowLoader {
   }
 };
 
+// candidate i of a row already gathered into LDS
+struct StagedLoader {
+  const int32_t* k;
+  const int64_t* v;
+  __device__ __forceinline__ void operator()(int i, int32_t& kk, int64_t& vv) const {
+    kk = k[i];
+    vv = v[i];
+  }
+};
+
 __device__ __forceinline__ CoarseRowLoader coarse_loader(const LevelView& lv, const int32_t* cmap,
                                                          const int32_t* cmem0,
                                                          const int32_t* cmem1, int32_t c,
@@ -527,10 +537,14 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
                                                           int32_t* tmpk, int64_t* tmpv,
                                                           int32_t* cnt, int64_t* tile_cnt,
                                                           const int32_t* longlist,
-                                                          int ntiles_c, unsigned char* lds, int bid_, int nblk_) {
-  // lds: kWin x (int64 + int32) bytes
+                                                          int ntiles_c, unsigned char* lds,
+                                                          bool staged, int bid_, int nblk_) {
+  // lds: kWin x (int64 + int32) bytes, and with `staged` another
+  // kSortCap x (int64 + int32) bytes that hold a whole row
   int64_t* acc = (int64_t*)lds;
   int32_t* cc = (int32_t*)(acc + kWin);
+  int64_t* stv = (int64_t*)(cc + kWin);
+  int32_t* stk = (int32_t*)(stv + kSortCap);
   __shared__ int32_t smi[kBlock / 64];
   __shared__ int64_t sml[kBlock / 64];
   const int32_t nlong = ctrl->nlong;
@@ -540,7 +554,34 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
     CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
     bool dummy = false;
     int k;
-    if (L <= kSortCap) {
+    if (staged && L <= kSortCap) {
+      // Gather the row into LDS once; when its coarse ids span few windows
+      // the dense merge runs over the staged copy (one LDS pass per window),
+      // otherwise the staged copy is sorted in place.
+      int32_t kmin = INT_MAX, kmax = -1;
+      for (int j = threadIdx.x; j < L; j += kBlock) {
+        int32_t kk;
+        int64_t vv;
+        ld(j, kk, vv);
+        stk[j] = kk;
+        stv[j] = vv;
+        if (kk != INT_MAX) {
+          kmin = kk < kmin ? kk : kmin;
+          kmax = kk > kmax ? kk : kmax;
+        }
+      }
+      kmin = block_min<kBlock, int32_t>(kmin, smi);
+      kmax = block_max<kBlock, int32_t>(kmax, smi);
+      const StagedLoader sl{stk, stv};
+      const int64_t nwin = kmax < 0 ? 0 : ((int64_t)kmax - kmin) / kWin + 1;
+      if (nwin <= 16) {
+        k = block_dense_emit<kBlock, true>(L, sl, acc, cc, smi, sml, tmpk + toff[c],
+                                           tmpv + toff[c], &dummy);
+      } else {
+        k = block_sort_emit<kBlock, true>(L, sl, cc, acc, tmpk + toff[c], tmpv + toff[c],
+                                          &dummy, smi);
+      }
+    } else if (L <= kSortCap) {
       // the LDS window doubles as the block sort's buffers
       k = block_sort_emit<kBlock, true>(L, ld, cc, acc, tmpk + toff[c], tmpv + toff[c], &dummy,
                                         smi);
