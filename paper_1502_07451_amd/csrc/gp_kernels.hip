@@ -432,9 +432,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
                     int64_t* partials, hipStream_t s) {
-  // a few rows per team amortise the block-completion tail; full-wave teams
-  // (long rows) keep one or two rows each so that the row loads stay in flight
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock * (TW == 64 ? 2 : 8));
+  // a few rows per team amortise the block-completion tail
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock * 8);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
   k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
   KCHECK();

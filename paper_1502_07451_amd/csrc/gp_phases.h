@@ -753,7 +753,27 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
       const int8_t pv = part[v];
       int64_t ext = 0, in = 0;
       const int32_t e1 = lv.xadj[v + 1];
-      for (int32_t e = lv.xadj[v] + lane; e < e1; e += TW) {
+      int32_t e = lv.xadj[v] + lane;
+      // four entries per lane in flight: their neighbour and side loads
+      // overlap instead of forming one dependent chain per entry
+      for (; e + 3 * TW < e1; e += 4 * TW) {
+        int32_t a[4];
+        int64_t ww[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          a[q] = lv.adj[e + q * TW];
+          ww[q] = lv.w[e + q * TW];
+        }
+        int8_t pq[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) pq[q] = part[a[q]];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          if (pq[q] != pv) ext += ww[q];
+          else in += ww[q];
+        }
+      }
+      for (; e < e1; e += TW) {
         const int64_t w = lv.w[e];
         if (part[lv.adj[e]] != pv) ext += w;
         else in += w;
