@@ -335,7 +335,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     __syncthreads();
     b_iso_pair(fv.b, sc.longlist, match, ctrl, 0, 1);
     __syncthreads();
-    b_contract_count(fv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles, 0, 1);
+    b_contract_count(fv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles, nullptr, 0, 1);
     __syncthreads();
     const int ntc = (f.n + kTileC - 1) / kTileC;
     b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,

@@ -93,7 +93,7 @@ struct gp_graph {
   // level scratch
   DBuf<int32_t> prop, tile_lead, cmem0, cmem1, cnt, tmpk, longlist;
   DBuf<int64_t> tile_ub, toff, tile_cnt, tmpv;
-  DBuf<int64_t> partials;  // 4 per block of a multi-block reduction (grids of <= 4096)
+  DBuf<int64_t> partials;  // <= 5 per block of a multi-block reduction (grids of <= 4096)
   DBuf<Cand> list;
   // initial bisection scratch
   DBuf<int64_t> i_tot, i_conn, i_res;
@@ -135,7 +135,7 @@ struct gp_graph {
            tile_ub.ensure(n1 / kTileV + 2) && cmem0.ensure(n1) && cmem1.ensure(n1) &&
            toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
            tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1) &&
-           partials.ensure(4 * 4096);
+           partials.ensure(5 * 4096);
   }
   bool ensure_init(int32_t nl, int K) {
     const int64_t kn = (int64_t)K * (nl > 0 ? nl : 1);
@@ -547,7 +547,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     if (!trace || l >= trace_cap) return GP_OK;
     Level* lvl = g->lv[l];
     LCHK(launch_final_stats(lvl->view(bal), lvl->vc.p, lvl->vg.p, lvl->part.p, g->ctrl,
-                            team_width_for(lvl->n, lvl->nnz), s));
+                            team_width_for(lvl->n, lvl->nnz), sc.partials, s));
     gp_status e2 = read_ctrl(g);
     if (e2 != GP_OK) return e2;
     int64_t* t = trace + 8 * l;
@@ -579,7 +579,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   }
   Level* l0 = g->lv[0];
   LCHK(launch_final_stats(l0->view(bal), l0->vc.p, l0->vg.p, l0->part.p, g->ctrl,
-                          team_width_for(l0->n, l0->nnz), s));
+                          team_width_for(l0->n, l0->nnz), sc.partials, s));
   const hipMemcpyKind kout =
       (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   HIPCHK(hipMemcpyAsync(part, l0->part.p, (size_t)n, kout, s));

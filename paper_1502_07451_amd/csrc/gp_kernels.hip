@@ -57,7 +57,11 @@ __global__ __launch_bounds__(kBlock) void k_twohop(LevelView lv, const int32_t* 
 __global__ __launch_bounds__(kBlock) void k_iso_count(LevelView lv, const int32_t* match,
                                                       Ctrl* ctrl, int32_t* tile_cnt,
                                                       int ntiles) {
-  b_iso_count(lv, match, ctrl, tile_cnt, ntiles, (int)blockIdx.x, (int)gridDim.x);
+  b_iso_count(lv, match, ctrl, tile_cnt, ntiles, (int)blockIdx.x, (int)gridDim.x, false);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iso_scan(Ctrl* ctrl, int32_t* tile_cnt, int ntiles) {
+  b_iso_scan(ctrl, tile_cnt, ntiles);
 }
 
 __global__ __launch_bounds__(kBlock) void k_iso_list(LevelView lv, const int32_t* match,
@@ -73,8 +77,16 @@ __global__ __launch_bounds__(kBlock) void k_iso_pair(const int64_t* b, const int
 
 __global__ __launch_bounds__(kBlock) void k_contract_count(LevelView lv, const int32_t* match,
                                                            Ctrl* ctrl, int32_t* tile_lead,
-                                                           int64_t* tile_ub, int ntiles) {
-  b_contract_count(lv, match, ctrl, tile_lead, tile_ub, ntiles, (int)blockIdx.x, (int)gridDim.x);
+                                                           int64_t* tile_ub, int ntiles,
+                                                           int64_t* partials) {
+  b_contract_count(lv, match, ctrl, tile_lead, tile_ub, ntiles, partials, (int)blockIdx.x,
+                   (int)gridDim.x, false);
+}
+
+__global__ __launch_bounds__(kBlock) void k_contract_scan(Ctrl* ctrl, int32_t* tile_lead,
+                                                          int64_t* tile_ub, int ntiles,
+                                                          const int64_t* partials, int nparts) {
+  b_contract_scan(ctrl, tile_lead, tile_ub, ntiles, partials, nparts);
 }
 
 __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int32_t* match,
@@ -108,7 +120,11 @@ __global__ __launch_bounds__(kBlock) void k_contract_long(LevelView lv, const in
                                                           int ntiles_c) {
   extern __shared__ __align__(16) unsigned char dyn_long[];
   b_contract_long(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist,
-                  ntiles_c, dyn_long, true, (int)blockIdx.x, (int)gridDim.x);
+                  ntiles_c, dyn_long, true, (int)blockIdx.x, (int)gridDim.x, false);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_scan(Ctrl* ctrl, int64_t* tile_cnt, int ntiles_c) {
+  b_tile_scan(ctrl, tile_cnt, ntiles_c);
 }
 
 __global__ __launch_bounds__(kBlock) void k_contract_compact(const Ctrl* ctrl,
@@ -127,13 +143,21 @@ __global__ __launch_bounds__(kBlock) void k_refine_gain(LevelView lv, const int8
                                                         RefCtl* rc, Cand* list,
                                                         int64_t* partials) {
   __shared__ SelShared sel;
-  b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x);
+  b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x, false);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_decide(int32_t n, RefCtl* rc, const Cand* list,
+                                                          const int64_t* partials, int nparts) {
+  __shared__ SelShared sel;
+  b_refine_decide(n, rc, list, partials, nparts, &sel);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_apply(int8_t* part, RefCtl* rc,
                                                          const Cand* list, int32_t* pass_out) {
-  b_refine_apply(part, rc, list, pass_out, (int)blockIdx.x, (int)gridDim.x);
+  b_refine_apply(part, rc, list, pass_out, (int)blockIdx.x, (int)gridDim.x, false);
 }
+
+__global__ void k_refine_finish(RefCtl* rc, int32_t* pass_out) { b_refine_finish(rc, pass_out); }
 
 __global__ __launch_bounds__(kBlock) void k_project(int32_t n, const int32_t* cmap,
                                                     const int8_t* cpart, int8_t* part, RefCtl* rc,
@@ -148,8 +172,13 @@ __global__ void k_start_level(RefCtl* rc, int npass) {
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_final_stats(LevelView lv, const int64_t* vc,
                                                         const int64_t* vg, const int8_t* part,
-                                                        Ctrl* ctrl) {
-  b_final_stats<TW>(lv, vc, vg, part, ctrl, (int)blockIdx.x, (int)gridDim.x);
+                                                        Ctrl* ctrl, int64_t* partials) {
+  b_final_stats<TW>(lv, vc, vg, part, ctrl, (int)blockIdx.x, (int)gridDim.x, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_reduce(Ctrl* ctrl, const int64_t* partials,
+                                                         int nparts) {
+  b_final_reduce(ctrl, partials, nparts);
 }
 
 __global__ void k_clear_stats(Ctrl* ctrl) {
@@ -362,6 +391,8 @@ bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratc
   ProfScope ps(PK_ISO, 0, 0.0, s);
   k_iso_count<<<g, kBlock, 0, s>>>(lv, match, ctrl, sc.tile_lead, ntiles);
   KCHECK();
+  k_iso_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_lead, ntiles);
+  KCHECK();
   k_iso_list<<<g, kBlock, 0, s>>>(lv, match, sc.tile_lead, sc.longlist, ntiles);
   KCHECK();
   k_iso_pair<<<grid_for(lv.n / 2 + 1, kBlock * 4), kBlock, 0, s>>>(lv.b, sc.longlist, match, ctrl);
@@ -377,8 +408,11 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
   const double n = lv.n;
   {
     ProfScope ps(PK_CONTRACT_COUNT, 0, 4 * n + 4 * (n + 1) + 8 * n, s);
-    k_contract_count<<<g, kBlock, 0, s>>>(lv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles);
+    k_contract_count<<<g, kBlock, 0, s>>>(lv, match, ctrl, sc.tile_lead, sc.tile_ub, ntiles,
+                                          sc.partials);
   }
+  KCHECK();
+  k_contract_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_lead, sc.tile_ub, ntiles, sc.partials, g);
   KCHECK();
   {
     ProfScope ps(PK_CONTRACT_MAP, 0, 4 * n + 4 * (n + 1) + 16 * n + 4 * n, s);
@@ -420,6 +454,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
                                             sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ntc1);
   }
   KCHECK();
+  k_tile_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_cnt, ntc1);
+  KCHECK();
   {
     ProfScope ps(PK_CONTRACT_COMPACT, 0, 0.0, s);
     k_contract_compact<<<g, kBlock, 0, s>>>(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv,
@@ -436,6 +472,8 @@ static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* l
   const int grid = grid_for((int64_t)lv.n * TW, kBlock * 8);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
   k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
+  KCHECK();
+  k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
   KCHECK();
   return true;
 }
@@ -457,6 +495,8 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
     k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list, pass_out);
   }
   KCHECK();
+  k_refine_finish<<<1, 64, 0, s>>>(rc, pass_out);
+  KCHECK();
   return true;
 }
 
@@ -475,18 +515,21 @@ bool launch_start_level(RefCtl* rc, int npass, hipStream_t s) {
 }
 
 bool launch_final_stats(const LevelView& lv, const int64_t* vc, const int64_t* vg,
-                        const int8_t* part, Ctrl* ctrl, int tw, hipStream_t s) {
-  k_clear_stats<<<1, 64, 0, s>>>(ctrl);
-  KCHECK();
+                        const int8_t* part, Ctrl* ctrl, int tw, int64_t* partials,
+                        hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * tw, kBlock * 2);
-  ProfScope ps(PK_FINAL_STATS, tw, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 25.0 * lv.n, s);
-  switch (tw) {
-    case 4: k_final_stats<4><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl); break;
-    case 8: k_final_stats<8><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl); break;
-    case 16: k_final_stats<16><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl); break;
-    case 32: k_final_stats<32><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl); break;
-    default: k_final_stats<64><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl); break;
+  {
+    ProfScope ps(PK_FINAL_STATS, tw, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 25.0 * lv.n, s);
+    switch (tw) {
+      case 4: k_final_stats<4><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl, partials); break;
+      case 8: k_final_stats<8><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl, partials); break;
+      case 16: k_final_stats<16><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl, partials); break;
+      case 32: k_final_stats<32><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl, partials); break;
+      default: k_final_stats<64><<<grid, kBlock, 0, s>>>(lv, vc, vg, part, ctrl, partials); break;
+    }
   }
+  KCHECK();
+  k_final_reduce<<<1, kBlock, 0, s>>>(ctrl, partials, grid);
   KCHECK();
   return true;
 }

@@ -19,7 +19,7 @@ struct Scratch {
   int64_t* tmpv;       // nnz
   int32_t* longlist;   // n
   Cand* list;          // n
-  int64_t* partials;   // 4 x 4096: per-block partial results of a reduction
+  int64_t* partials;   // 5 x 4096: per-block partial results of a reduction
 };
 
 // scratch of the initial bisection, sized for the coarsest graph and K trials
@@ -86,8 +86,10 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
                     int npass, hipStream_t s);
 bool launch_start_level(RefCtl* rc, int npass, hipStream_t s);
+// partials: 5 int64 per block (grids are capped at 4096)
 bool launch_final_stats(const LevelView& lv, const int64_t* vc, const int64_t* vg,
-                        const int8_t* part, Ctrl* ctrl, int tw, hipStream_t s);
+                        const int8_t* part, Ctrl* ctrl, int tw, int64_t* partials,
+                        hipStream_t s);
 bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, const InitScratch& is,
                  int8_t* out_part, hipStream_t s);
 bool launch_validate(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,

@@ -204,9 +204,29 @@ __device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub,
 }
 
 // unmatched vertices without neighbours, paired in ascending id
+// exclusive scan of the isolated-vertex tile counts (one block)
+__device__ __forceinline__ void b_iso_scan(Ctrl* ctrl, int32_t* tile_cnt, int ntiles) {
+  __shared__ int32_t smi[kBlock / 64];
+  int32_t carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    const int32_t x = t < ntiles ? tile_cnt[t] : 0;
+    int32_t tot;
+    const int32_t ex = block_exscan<kBlock, int32_t>(x, smi, &tot);
+    if (t < ntiles) tile_cnt[t] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctrl->niso = carry;
+}
+
+// Multi-block phases end without a completion count: on a multi-die GPU the
+// release fence each finishing block would need writes its L2 back, which
+// costs far more than a separate one-block launch for the tail.  The batched
+// path (one block per graph) runs the tail inline (inline_tail).
 __device__ __forceinline__ void b_iso_count(LevelView lv, const int32_t* match,
                                                       Ctrl* ctrl, int32_t* tile_cnt,
-                                                      int ntiles, int bid_, int nblk_) {
+                                                      int ntiles, int bid_, int nblk_,
+                                                      bool inline_tail = true) {
   __shared__ int32_t smi[kBlock / 64];
   for (int t = bid_; t < ntiles; t += nblk_) {
     int32_t c = 0;
@@ -218,17 +238,9 @@ __device__ __forceinline__ void b_iso_count(LevelView lv, const int32_t* match,
     c = block_sum<kBlock, int32_t>(c, smi);
     if (threadIdx.x == 0) tile_cnt[t] = c;
   }
-  if (!tail_gate(&ctrl->ctr_iso, nblk_)) return;
-  int32_t carry = 0;
-  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
-    const int t = t0 + threadIdx.x;
-    const int32_t x = t < ntiles ? tile_cnt[t] : 0;
-    int32_t tot;
-    const int32_t ex = block_exscan<kBlock, int32_t>(x, smi, &tot);
-    if (t < ntiles) tile_cnt[t] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) ctrl->niso = carry;
+  if (!inline_tail) return;
+  __syncthreads();
+  b_iso_scan(ctrl, tile_cnt, ntiles);
 }
 
 __device__ __forceinline__ void b_iso_list(LevelView lv, const int32_t* match,
@@ -267,9 +279,14 @@ __device__ __forceinline__ void b_iso_pair(const int64_t* b, const int32_t* iso,
 
 // --------------------------------------------------------------- contraction
 // tile t covers fine vertices [t*kTileV, (t+1)*kTileV); each thread 4 of them
+__device__ __forceinline__ void b_contract_scan(Ctrl* ctrl, int32_t* tile_lead, int64_t* tile_ub,
+                                                int ntiles, const int64_t* partials,
+                                                int nparts);
+
 __device__ __forceinline__ void b_contract_count(LevelView lv, const int32_t* match,
                                                            Ctrl* ctrl, int32_t* tile_lead,
-                                                           int64_t* tile_ub, int ntiles, int bid_, int nblk_) {
+                                                           int64_t* tile_ub, int ntiles, int64_t* partials, int bid_, int nblk_,
+                                                           bool inline_tail = true) {
   __shared__ int64_t sml[kBlock / 64];
   __shared__ int32_t smi[kBlock / 64];
   int64_t mx = 0;
@@ -300,9 +317,28 @@ __device__ __forceinline__ void b_contract_count(LevelView lv, const int32_t* ma
     }
   }
   mx = block_max<kBlock, int64_t>(mx, sml);
-  if (threadIdx.x == 0) atomicMax((long long*)&ctrl->maxb_next, (long long)mx);
-  if (!tail_gate(&ctrl->ctr_count, nblk_)) return;
-  // exclusive scan of the tile totals
+  if (!inline_tail) {
+    if (threadIdx.x == 0) partials[bid_] = mx;  // largest merged weight of this block
+    return;
+  }
+  if (threadIdx.x == 0) ctrl->maxb_next = mx > ctrl->maxb_next ? mx : ctrl->maxb_next;
+  __syncthreads();
+  b_contract_scan(ctrl, tile_lead, tile_ub, ntiles, nullptr, 0);
+}
+
+// exclusive scans of the leader and entry-bound tile totals (one block); with
+// partials, also the largest merged balance weight over nparts blocks
+__device__ __forceinline__ void b_contract_scan(Ctrl* ctrl, int32_t* tile_lead, int64_t* tile_ub,
+                                                int ntiles, const int64_t* partials,
+                                                int nparts) {
+  __shared__ int64_t sml[kBlock / 64];
+  __shared__ int32_t smi[kBlock / 64];
+  if (partials) {
+    int64_t mx = 0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) mx = partials[i] > mx ? partials[i] : mx;
+    mx = block_max<kBlock, int64_t>(mx, sml);
+    if (threadIdx.x == 0) ctrl->maxb_next = mx > ctrl->maxb_next ? mx : ctrl->maxb_next;
+  }
   int32_t carry_l = 0;
   int64_t carry_u = 0;
   for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
@@ -530,6 +566,22 @@ __device__ __forceinline__ void b_contract_rows(
   }
 }
 
+// exclusive scan of the coarse-tile entry counts; their total is 2m of the
+// coarse level (one block)
+__device__ __forceinline__ void b_tile_scan(Ctrl* ctrl, int64_t* tile_cnt, int ntiles_c) {
+  __shared__ int64_t sml[kBlock / 64];
+  int64_t carry = 0;
+  for (int t0 = 0; t0 < ntiles_c; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    int64_t x = t < ntiles_c ? tile_cnt[t] : 0;
+    int64_t tot;
+    int64_t e = block_exscan<kBlock, int64_t>(x, sml, &tot);
+    if (t < ntiles_c) tile_cnt[t] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctrl->nnz_c = (int32_t)carry;
+}
+
 __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cmap,
                                                           const int32_t* cmem0,
                                                           const int32_t* cmem1,
@@ -538,7 +590,8 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
                                                           int32_t* cnt, int64_t* tile_cnt,
                                                           const int32_t* longlist,
                                                           int ntiles_c, unsigned char* lds,
-                                                          bool staged, int bid_, int nblk_) {
+                                                          bool staged, int bid_, int nblk_,
+                                                          bool inline_tail = true) {
   // lds: kWin x (int64 + int32) bytes, and with `staged` another
   // kSortCap x (int64 + int32) bytes that hold a whole row
   int64_t* acc = (int64_t*)lds;
@@ -594,17 +647,9 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
       atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
     }
   }
-  if (!tail_gate(&ctrl->ctr_long, nblk_)) return;
-  int64_t carry = 0;
-  for (int t0 = 0; t0 < ntiles_c; t0 += kBlock) {
-    const int t = t0 + threadIdx.x;
-    int64_t x = t < ntiles_c ? tile_cnt[t] : 0;
-    int64_t tot;
-    int64_t e = block_exscan<kBlock, int64_t>(x, sml, &tot);
-    if (t < ntiles_c) tile_cnt[t] = carry + e;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) ctrl->nnz_c = (int32_t)carry;
+  if (!inline_tail) return;
+  __syncthreads();
+  b_tile_scan(ctrl, tile_cnt, ntiles_c);
 }
 
 __device__ __forceinline__ void b_contract_compact(const Ctrl* ctrl,
@@ -728,10 +773,16 @@ __device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_b, int64_t
   clear_pass_acc(rc);
 }
 
+__device__ __forceinline__ void refine_decide_common(int32_t n, RefCtl* rc, const Cand* list,
+                                                     SelShared* sel, int mode, int s,
+                                                     int64_t ext_acc, int64_t cb, int64_t gmn,
+                                                     int64_t gmx);
+
 template <int TW>
 __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list, SelShared* sel,
-                                                        int64_t* partials, int bid_, int nblk_) {
+                                                        int64_t* partials, int bid_, int nblk_,
+                                                        bool inline_tail = true) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   int mode, s;
@@ -800,31 +851,25 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
   cb = block_sum<kBlock, int64_t>(cb, sml);
   gmn = block_min<kBlock, int64_t>(gmn, sml);
   gmx = block_max<kBlock, int64_t>(gmx, sml);
-  if (nblk_ > 1) {
-    // per-block partials (4 x nblk int64) instead of atomics on four shared
-    // words, which serialise in L2 when hundreds of blocks finish together
+  if (!inline_tail) {
+    // per-block partials (4 x nblk int64), reduced by the decision launch
     if (threadIdx.x == 0) {
       partials[4 * bid_ + 0] = ext_acc;
       partials[4 * bid_ + 1] = cb;
       partials[4 * bid_ + 2] = gmn;
       partials[4 * bid_ + 3] = gmx;
     }
-    if (!last_block(&rc->ctr_gain, (uint32_t)nblk_)) return;
-    ext_acc = 0;
-    cb = 0;
-    gmn = INT64_MAX;
-    gmx = INT64_MIN;
-    for (int i = threadIdx.x; i < nblk_; i += kBlock) {
-      ext_acc += partials[4 * i + 0];
-      cb += partials[4 * i + 1];
-      gmn = partials[4 * i + 2] < gmn ? partials[4 * i + 2] : gmn;
-      gmx = partials[4 * i + 3] > gmx ? partials[4 * i + 3] : gmx;
-    }
-    ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
-    cb = block_sum<kBlock, int64_t>(cb, sml);
-    gmn = block_min<kBlock, int64_t>(gmn, sml);
-    gmx = block_max<kBlock, int64_t>(gmx, sml);
+    return;
   }
+  __syncthreads();
+  refine_decide_common(lv.n, rc, list, sel, mode, s, ext_acc, cb, gmn, gmx);
+}
+
+// the pass totals are known: record them and choose the admitted prefix
+__device__ __forceinline__ void refine_decide_common(int32_t n, RefCtl* rc, const Cand* list,
+                                                     SelShared* sel, int mode, int s,
+                                                     int64_t ext_acc, int64_t cb, int64_t gmn,
+                                                     int64_t gmx) {
   if (threadIdx.x == 0) {
     rc->ext_sum = ext_acc;
     rc->cand_b = cb;
@@ -836,11 +881,42 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
   __syncthreads();
   const uint32_t ncand = rc->ncand;
   const ListItems items{list, ncand};
-  decide_admission<kBlock>(rc, items, ncand, cb, gmn, gmx, lv.n, sel);
+  decide_admission<kBlock>(rc, items, ncand, cb, gmn, gmx, n, sel);
+}
+
+// one block: reduce the gain launch's per-block partials, then decide
+__device__ __forceinline__ void b_refine_decide(int32_t n, RefCtl* rc, const Cand* list,
+                                                const int64_t* partials, int nparts,
+                                                SelShared* sel) {
+  __shared__ int64_t sml[kBlock / 64];
+  if (rc->done) return;
+  int mode, s;
+  plan_pass(*rc, &mode, &s);
+  int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+    ext_acc += partials[4 * i + 0];
+    cb += partials[4 * i + 1];
+    gmn = partials[4 * i + 2] < gmn ? partials[4 * i + 2] : gmn;
+    gmx = partials[4 * i + 3] > gmx ? partials[4 * i + 3] : gmx;
+  }
+  ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+  cb = block_sum<kBlock, int64_t>(cb, sml);
+  gmn = block_min<kBlock, int64_t>(gmn, sml);
+  gmx = block_max<kBlock, int64_t>(gmx, sml);
+  refine_decide_common(n, rc, list, sel, mode, s, ext_acc, cb, gmn, gmx);
+}
+
+__device__ __forceinline__ void b_refine_finish(RefCtl* rc, int32_t* pass_out) {
+  if (rc->done) return;
+  if (threadIdx.x == 0) {
+    finish_pass(rc, rc->moved_b, rc->moved_n);
+    *pass_out = rc->pass;
+  }
 }
 
 __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
-                                                         const Cand* list, int32_t* pass_out, int bid_, int nblk_) {
+                                                         const Cand* list, int32_t* pass_out, int bid_, int nblk_,
+                                                         bool inline_tail = true) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   const RefCtl r = *rc;
@@ -861,11 +937,9 @@ __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
     atomicAdd((unsigned long long*)&rc->moved_b, (unsigned long long)mb);
     atomicAdd((unsigned long long*)&rc->moved_n, (unsigned long long)mn);
   }
-  if (!tail_gate(&rc->ctr_apply, nblk_)) return;
-  if (threadIdx.x == 0) {
-    finish_pass(rc, rc->moved_b, rc->moved_n);
-    *pass_out = rc->pass;
-  }
+  if (!inline_tail) return;
+  __syncthreads();
+  b_refine_finish(rc, pass_out);
 }
 
 __device__ __forceinline__ void start_level(RefCtl* rc, int npass) {
@@ -894,7 +968,8 @@ __device__ __forceinline__ void b_start_level(RefCtl* rc, int npass, int bid_, i
 template <int TW>
 __device__ __forceinline__ void b_final_stats(LevelView lv, const int64_t* vc,
                                                         const int64_t* vg, const int8_t* part,
-                                                        Ctrl* ctrl, int bid_, int nblk_) {
+                                                        Ctrl* ctrl, int bid_, int nblk_,
+                                                        int64_t* partials = nullptr) {
   __shared__ int64_t sml[kBlock / 64];
   const int lane = threadIdx.x & (TW - 1);
   const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
@@ -924,11 +999,35 @@ __device__ __forceinline__ void b_final_stats(LevelView lv, const int64_t* vc,
   t0 = block_sum<kBlock, int64_t>(t0, sml);
   t1 = block_sum<kBlock, int64_t>(t1, sml);
   if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&ctrl->res_ext, (unsigned long long)ext_acc);
-    atomicAdd((unsigned long long*)&ctrl->res_load[0], (unsigned long long)l0);
-    atomicAdd((unsigned long long*)&ctrl->res_load[1], (unsigned long long)l1);
-    atomicAdd((unsigned long long*)&ctrl->res_time[0], (unsigned long long)t0);
-    atomicAdd((unsigned long long*)&ctrl->res_time[1], (unsigned long long)t1);
+    if (partials) {  // per-block partials, summed by b_final_reduce
+      partials[5 * bid_ + 0] = ext_acc;
+      partials[5 * bid_ + 1] = l0;
+      partials[5 * bid_ + 2] = l1;
+      partials[5 * bid_ + 3] = t0;
+      partials[5 * bid_ + 4] = t1;
+    } else {
+      atomicAdd((unsigned long long*)&ctrl->res_ext, (unsigned long long)ext_acc);
+      atomicAdd((unsigned long long*)&ctrl->res_load[0], (unsigned long long)l0);
+      atomicAdd((unsigned long long*)&ctrl->res_load[1], (unsigned long long)l1);
+      atomicAdd((unsigned long long*)&ctrl->res_time[0], (unsigned long long)t0);
+      atomicAdd((unsigned long long*)&ctrl->res_time[1], (unsigned long long)t1);
+    }
+  }
+}
+
+// one block: totals of b_final_stats' per-block partials
+__device__ __forceinline__ void b_final_reduce(Ctrl* ctrl, const int64_t* partials, int nparts) {
+  __shared__ int64_t sml[kBlock / 64];
+  int64_t v[5] = {0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nparts; i += kBlock)
+    for (int q = 0; q < 5; q++) v[q] += partials[5 * i + q];
+  for (int q = 0; q < 5; q++) v[q] = block_sum<kBlock, int64_t>(v[q], sml);
+  if (threadIdx.x == 0) {
+    ctrl->res_ext = v[0];
+    ctrl->res_load[0] = v[1];
+    ctrl->res_load[1] = v[2];
+    ctrl->res_time[0] = v[3];
+    ctrl->res_time[1] = v[4];
   }
 }
 
