@@ -331,7 +331,7 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s) {
 template <int TW>
 static bool propose_tw(const LevelView& lv, const int32_t* match, int32_t* prop, const Ctrl* ctrl,
                        int round, uint64_t hs, hipStream_t s) {
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock * 2);
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
   const double n = lv.n, m2 = lv.nnz;
   ProfScope ps(PK_MATCH_PROPOSE, TW, round == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
   k_match_propose<TW><<<grid, kBlock, 0, s>>>(lv, match, prop, ctrl, round, hs);
@@ -468,8 +468,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
                     int64_t* partials, hipStream_t s) {
-  // a few rows per team amortise the block-completion tail
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock * 8);
+  // one row per team: the row loads of all vertices are in flight at once
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
   k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
   KCHECK();
