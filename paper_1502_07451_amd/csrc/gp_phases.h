@@ -478,12 +478,12 @@ __device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32
   if (lane == 0) *cnt_out = cnt;
 }
 
-// Rows are sorted in groups of 16 per block: one 16-lane team per short row
+// Rows are sorted in small groups per block: one 16-lane team per short row
 // (<= 16 candidates), and for longer rows one wave per row (in registers up
 // to 64, in the wave's private LDS up to kWaveCap); rows beyond that go to
 // the long list.  Many small groups keep enough rows in flight to hide the
 // gather latency at the coarse levels, where rows are long and few.
-constexpr int kRowsPerBlock = 16;
+constexpr int kRowsPerBlock = 4;
 
 __device__ __forceinline__ void b_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
@@ -496,7 +496,9 @@ __device__ __forceinline__ void b_contract_rows(
   __shared__ int32_t s_e0[kRowsPerBlock], s_d0[kRowsPerBlock], s_e1[kRowsPerBlock],
       s_len[kRowsPerBlock];
   static_assert(kWaveCap * (kBlock / 64) <= kRowBlockCap, "wave regions exceed the block region");
-  static_assert(kRowsPerBlock == 16 && kBlock == 256, "16 teams of 16 lanes, 4 rows per wave");
+  static_assert(kRowsPerBlock <= kBlock / 16 && kRowsPerBlock % (kBlock / 64) == 0,
+                "a 16-lane team per row and whole rows per wave");
+  constexpr int kRowsPerWave = kRowsPerBlock / (kBlock / 64);
   static_assert(kTileC % kRowsPerBlock == 0, "row groups nest in compaction tiles");
   (void)ntiles_c;
   const int32_t nc = ctrl->nc;
@@ -536,8 +538,8 @@ __device__ __forceinline__ void b_contract_rows(
         team_row<16>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
       }
     }
-    for (int q = 0; q < 4; q++) {
-      const int i = 4 * wave + q;
+    for (int q = 0; q < kRowsPerWave; q++) {
+      const int i = kRowsPerWave * wave + q;
       if (i >= rows) break;
       const int L = s_len[i];
       if (L <= 16) continue;
