@@ -508,11 +508,9 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     const uint64_t hs = host_mix64(o->seed ^ (uint64_t)(uint32_t)L);
     if (R == 0) HIPCHK(hipMemsetAsync(f->match.p, 0xff, sizeof(int32_t) * f->n, s));
     g->prof.level = L;
-    for (int rr = 0; rr < R; rr++) {
-      g->prof.idx = rr;
-      LCHK(launch_match_round(fv, f->match.p, sc.prop, g->ctrl, rr, hs, tw, s));
-    }
     g->prof.idx = 0;
+    // the long-row list is free during matching: it is the second proposal buffer
+    LCHK(launch_match_rounds(fv, f->match.p, sc.prop, sc.longlist, g->ctrl, R, hs, tw, s));
     LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));

@@ -43,6 +43,20 @@ __global__ __launch_bounds__(kBlock) void k_match_resolve(int32_t n, int32_t* ma
 }
 
 template <int TW>
+__global__ __launch_bounds__(kBlock) void k_match_round(LevelView lv, int32_t* match,
+                                                        const int32_t* prop_prev,
+                                                        int32_t* prop_cur, const Ctrl* ctrl,
+                                                        int round, uint64_t hs) {
+  b_match_round<TW>(lv, match, prop_prev, prop_cur, ctrl, round, hs, (int)blockIdx.x,
+                    (int)gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_match_settle(int32_t n, int32_t* match,
+                                                         const int32_t* prop) {
+  b_match_settle(n, match, prop, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <int TW>
 __global__ __launch_bounds__(kBlock) void k_hub(LevelView lv, const int32_t* match, int32_t* hub,
                                                 uint64_t hs) {
   b_hub<TW>(lv, match, hub, hs, (int)blockIdx.x, (int)gridDim.x);
@@ -335,6 +349,39 @@ static bool propose_tw(const LevelView& lv, const int32_t* match, int32_t* prop,
   const double n = lv.n, m2 = lv.nnz;
   ProfScope ps(PK_MATCH_PROPOSE, TW, round == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
   k_match_propose<TW><<<grid, kBlock, 0, s>>>(lv, match, prop, ctrl, round, hs);
+  KCHECK();
+  return true;
+}
+
+template <int TW>
+static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t* pb,
+                      const Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
+  const double n = lv.n, m2 = lv.nnz;
+  for (int r = 0; r < R; r++) {
+    int32_t* cur = (r & 1) ? pb : pa;
+    const int32_t* prev = (r & 1) ? pa : pb;
+    ProfScope ps(PK_MATCH_PROPOSE, TW, r == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
+    k_match_round<TW><<<grid, kBlock, 0, s>>>(lv, match, prev, cur, ctrl, r, hs);
+  }
+}
+
+bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
+                         const Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s) {
+  if (R <= 0) return true;
+  switch (tw) {
+    case 4: rounds_tw<4>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 8: rounds_tw<8>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 16: rounds_tw<16>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 32: rounds_tw<32>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+    default: rounds_tw<64>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+  }
+  KCHECK();
+  {
+    ProfScope ps(PK_MATCH_RESOLVE, 0, 0.0, s);
+    k_match_settle<<<grid_for(lv.n, kBlock * 4), kBlock, 0, s>>>(lv.n, match,
+                                                                  ((R - 1) & 1) ? prop_b : prop_a);
+  }
   KCHECK();
   return true;
 }

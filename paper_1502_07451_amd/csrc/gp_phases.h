@@ -121,6 +121,85 @@ __device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
   if (threadIdx.x == 0 && made) atomicAdd(&ctrl->made[round], made);
 }
 
+// One matching round that also settles the previous one (single-graph
+// path): round r's kernel first makes the mutual proposals of round r-1
+// final for its own vertex, then proposes among the neighbours that are
+// still free.  A neighbour v is free when match[v] is -1 and v's round r-1
+// proposal was not mutual; v's own thread may be storing the settled value
+// at the same time, but both reads give the same answer.  Proposals are
+// double-buffered (prop_prev, prop_cur), and b_match_settle settles the last
+// round.  Rounds after one that matched nothing repeat its proposals and
+// match nothing, so running them all yields the same matching as stopping.
+template <int TW>
+__device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
+                                              const int32_t* prop_prev, int32_t* prop_cur,
+                                              const Ctrl* ctrl, int round, uint64_t hs,
+                                              int bid_, int nblk_) {
+  const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t uu = team; uu < lv.n; uu += nteams) {
+    const int32_t u = (int32_t)uu;
+    int32_t mu = -1;
+    if (round > 0) {
+      mu = match[u];
+      if (mu == -1) {
+        const int32_t p = prop_prev[u];
+        if (p >= 0 && prop_prev[p] == u) {
+          mu = p;
+          if (lane == 0) match[u] = p;
+        }
+      }
+    } else if (lane == 0) {
+      match[u] = -1;
+    }
+    if (mu != -1) {
+      if (lane == 0) prop_cur[u] = -1;
+      continue;
+    }
+    const int64_t bu = lv.b[u];
+    const bool capcheck = bu + maxb > cap;
+    int64_t bw = -1;
+    int32_t bv = -1;
+    const int32_t e1 = lv.xadj[u + 1];
+    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
+      const int32_t v = lv.adj[e];
+      if (round > 0) {
+        if (match[v] != -1) continue;
+        const int32_t pv = prop_prev[v];
+        if (pv >= 0 && prop_prev[pv] == v) continue;
+      }
+      if (capcheck && bu + lv.b[v] > cap) continue;
+      const int64_t w = lv.w[e];
+      if (match_better(w, v, bw, bv, hs, u)) {
+        bw = w;
+        bv = v;
+      }
+    }
+    butterfly<TW>([&](auto o) {
+      const int64_t ow = xor_lane<decltype(o)::value>(bw);
+      const int32_t ov = xor_lane<decltype(o)::value>(bv);
+      if (match_better(ow, ov, bw, bv, hs, u)) {
+        bw = ow;
+        bv = ov;
+      }
+    });
+    if (lane == 0) prop_cur[u] = bv;
+  }
+}
+
+// settles the mutual proposals of the last round
+__device__ __forceinline__ void b_match_settle(int32_t n, int32_t* match, const int32_t* prop,
+                                               int bid_, int nblk_) {
+  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
+       u += (int64_t)nblk_ * kBlock) {
+    if (match[u] != -1) continue;
+    const int32_t p = prop[u];
+    if (p >= 0 && prop[p] == (int32_t)u) match[u] = p;
+  }
+}
+
 // --------------------------------------------------------------- two-hop pass
 // hub[u] = first neighbour of an unmatched u under the edge order (-1: none);
 // matched vertices get -2
