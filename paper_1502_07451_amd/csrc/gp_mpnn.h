@@ -30,6 +30,21 @@ struct MpScratch {
   int32_t* order; // n
 };
 
+// phi(x) = (bitlen(x) - 1) + (the 8 bits after the leading one) / 256, and 0
+// for x <= 0.  Computed on 32-bit words: the leading word is normalised so
+// that its top bit is the leading one, then the next 8 bits are read off.
+// No 64-bit shift by a variable amount appears, so the float conversions are
+// 32-bit too (see the shift check in the build script).
+__device__ __forceinline__ float mp_phi(int64_t x) {
+  if (x <= 0) return 0.0f;
+  const uint32_t hi = (uint32_t)((uint64_t)x >> 32), lo = (uint32_t)(uint64_t)x;
+  const uint32_t t = hi ? hi : lo, tl = hi ? lo : 0u;
+  const int c = __clz((int)t);
+  const uint32_t top = c ? ((t << c) | (tl >> (32 - c))) : t;
+  const uint32_t e = (hi ? 63u : 31u) - (uint32_t)c;
+  return (float)e + (float)((top >> 23) & 0xffu) * (1.0f / 256.0f);
+}
+
 inline int next_pow2_host(int x) {
   int p = 2;
   while (p < x) p <<= 1;

@@ -42,15 +42,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 __device__ __forceinline__ float relu_f(float a) { return a > 0.0f ? a : 0.0f; }
 
-__device__ __forceinline__ float phi_f(int64_t x) {
-  if (x <= 0) return 0.0f;
-  const int L = 64 - __clzll((unsigned long long)x);
-  uint64_t f;
-  if (L - 1 >= 8) f = ((uint64_t)x >> (L - 1 - 8)) & 0xffu;
-  else f = ((uint64_t)x << (8 - (L - 1))) & 0xffu;
-  return (float)(L - 1) + (float)f * (1.0f / 256.0f);
-}
-
 // input layer: one wave per vertex, lane j computes h0[j]
 __global__ __launch_bounds__(kBlock) void k_mp_input(LevelView lv, const int64_t* vc,
                                                      const int64_t* vg, const uint16_t* P,
@@ -64,12 +55,12 @@ __global__ __launch_bounds__(kBlock) void k_mp_input(LevelView lv, const int64_t
     for (int32_t q = e0 + lane; q < e1; q += 64) tw += lv.w[q];
     tw = team_sum<64>(tw);
     const int64_t deg = e1 - e0;
-    float x[4] = {phi_f(vc[v]), phi_f(vg[v]), phi_f(deg), phi_f(tw)};
+    float x[4] = {mp_phi(vc[v]), mp_phi(vg[v]), mp_phi(deg), mp_phi(tw)};
     float acc = bf2f(P[kMpOffBin + lane]);
 #pragma unroll
     for (int k = 0; k < 4; k++) acc = __builtin_fmaf(bf2f(P[kMpOffWin + lane * 4 + k]), x[k], acc);
     h0[v * kMpH + lane] = f2bf(relu_f(acc));
-    if (lane == 0) inv[v] = deg > 0 ? __frcp_rn((float)deg) : 0.0f;
+    if (lane == 0) inv[v] = e1 > e0 ? __frcp_rn((float)(e1 - e0)) : 0.0f;
   }
 }
 
@@ -96,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(LevelView lv, const uint16_
   for (int64_t v = wv; v < lv.n; v += nw) {
     float acc = 0.0f;
     for (int32_t q = lv.xadj[v]; q < lv.xadj[v + 1]; q++) {
-      const float e = phi_f(lv.w[q]) / 64.0f;
+      const float e = mp_phi(lv.w[q]) / 64.0f;
       acc = __builtin_fmaf(e, bf2f(hin[(int64_t)lv.adj[q] * kMpH + lane]), acc);
     }
     const float m = bf2f(f2bf(acc * inv[v]));

@@ -41,15 +41,6 @@ __device__ __forceinline__ uint16_t tf2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float tphi(int64_t x) {
-  if (x <= 0) return 0.0f;
-  const int L = 64 - __clzll((unsigned long long)x);
-  uint64_t f;
-  if (L - 1 >= 8) f = ((uint64_t)x >> (L - 1 - 8)) & 0xffu;
-  else f = ((uint64_t)x << (8 - (L - 1))) & 0xffu;
-  return (float)(L - 1) + (float)f * (1.0f / 256.0f);
-}
-
 // ------------------------------------------------------------- training set
 // Global-id CSR of all training graphs (graph g: vertices voff[g]..voff[g+1]),
 // per-vertex inputs x (4), 1/deg, loss weight b_v / W_g and label, per-entry
@@ -87,17 +78,17 @@ __global__ __launch_bounds__(kBlock) void k_tr_prep(int32_t G, const int64_t* vo
       int64_t tw = 0;
       for (int32_t q = a; q < b; q++) {
         d.adj[e0 + q] = (int32_t)(v0 + adj[e0 + q]);
-        d.e[e0 + q] = tphi(w[e0 + q]) / 64.0f;
+        d.e[e0 + q] = mp_phi(w[e0 + q]) / 64.0f;
         tw += w[e0 + q];
       }
       d.xadj[gv] = e0 + a;
       if (v == n - 1) d.xadj[gv + 1] = e0 + b;
       const int64_t deg = b - a;
-      d.x[4 * gv + 0] = tphi(vwgt[2 * gv]);
-      d.x[4 * gv + 1] = tphi(vwgt[2 * gv + 1]);
-      d.x[4 * gv + 2] = tphi(deg);
-      d.x[4 * gv + 3] = tphi(tw);
-      d.inv[gv] = deg > 0 ? __frcp_rn((float)deg) : 0.0f;
+      d.x[4 * gv + 0] = mp_phi(vwgt[2 * gv]);
+      d.x[4 * gv + 1] = mp_phi(vwgt[2 * gv + 1]);
+      d.x[4 * gv + 2] = mp_phi(deg);
+      d.x[4 * gv + 3] = mp_phi(tw);
+      d.inv[gv] = b > a ? __frcp_rn((float)(b - a)) : 0.0f;
       const int64_t bv = vwgt[2 * gv + bal];
       d.cw[gv] = W > 0 ? (float)((double)bv / (double)W) : 1.0f / (float)n;
       d.y[gv] = label[gv] ? 1.0f : 0.0f;
