@@ -160,6 +160,42 @@ __device__ __forceinline__ T block_min(T v, T* sm) {
   return r;
 }
 
+// (sum a, sum b, min c, max d) over the block with one LDS exchange; sm
+// holds 4 * BS/64 elements; every thread gets the results
+template <int BS>
+__device__ __forceinline__ void block_sum_sum_min_max(int64_t& a, int64_t& b, int64_t& c,
+                                                      int64_t& d, int64_t* sm) {
+  butterfly<64>([&](auto o) {
+    a += xor_lane<decltype(o)::value>(a);
+    b += xor_lane<decltype(o)::value>(b);
+    const int64_t c2 = xor_lane<decltype(o)::value>(c);
+    const int64_t d2 = xor_lane<decltype(o)::value>(d);
+    c = c2 < c ? c2 : c;
+    d = d2 > d ? d2 : d;
+  });
+  constexpr int W = BS / 64;
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 0) {
+    sm[w] = a;
+    sm[W + w] = b;
+    sm[2 * W + w] = c;
+    sm[3 * W + w] = d;
+  }
+  __syncthreads();
+  a = sm[0];
+  b = sm[W];
+  c = sm[2 * W];
+  d = sm[3 * W];
+#pragma unroll
+  for (int i = 1; i < W; i++) {
+    a += sm[i];
+    b += sm[W + i];
+    c = sm[2 * W + i] < c ? sm[2 * W + i] : c;
+    d = sm[3 * W + i] > d ? sm[3 * W + i] : d;
+  }
+  __syncthreads();
+}
+
 // exclusive prefix over the block in thread order; *total = block sum.
 template <int BS, class T>
 __device__ __forceinline__ T block_exscan(T v, T* sm, T* total) {

@@ -1366,7 +1366,7 @@ template <int BS>
 __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* s_b,
                            int8_t* s_part, int8_t* s_mv, RefCtl& srf, SelShared& sel) {
   const int32_t n = lv.n;
-  __shared__ int64_t sml[BS / 64];
+  __shared__ int64_t sm4[4 * (BS / 64)];
   for (;;) {
     if (srf.done) break;
     int mode, s;
@@ -1381,10 +1381,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
       gmn = c.gain < gmn ? c.gain : gmn;
       gmx = c.gain > gmx ? c.gain : gmx;
     }
-    cb = block_sum<BS, int64_t>(cb, sml);
-    cnt = block_sum<BS, int64_t>(cnt, sml);
-    gmn = block_min<BS, int64_t>(gmn, sml);
-    gmx = block_max<BS, int64_t>(gmx, sml);
+    block_sum_sum_min_max<BS>(cb, cnt, gmn, gmx, sm4);
     if (threadIdx.x == 0) {
       srf.mode = mode;
       srf.s = s;
@@ -1392,22 +1389,19 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
     __syncthreads();
     decide_admission<BS>(&srf, items, (uint32_t)cnt, cb, gmn, gmx, n, &sel);
     __syncthreads();
+    // admitted vertices change side (each thread only touches its own)
     const int d = 1 - s;
     int64_t mb = 0, mn = 0;
     for (int32_t v = threadIdx.x; v < n; v += BS) {
       Cand c;
       if (items.get(v, c) && admitted(srf, c)) {
         s_mv[v] = 1;
+        s_part[v] = (int8_t)d;
+        s_gain[v] = -c.gain;
         mb += c.b;
         mn++;
       }
     }
-    __syncthreads();
-    for (int32_t v = threadIdx.x; v < n; v += BS)
-      if (s_mv[v]) {
-        s_part[v] = (int8_t)d;
-        s_gain[v] = -s_gain[v];
-      }
     __syncthreads();
     for (int32_t v = threadIdx.x; v < n; v += BS)
       if (s_mv[v]) {
@@ -1419,8 +1413,8 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
         }
         s_mv[v] = 0;
       }
-    mb = block_sum<BS, int64_t>(mb, sml);
-    mn = block_sum<BS, int64_t>(mn, sml);
+    int64_t unused_min = 0, unused_max = 0;
+    block_sum_sum_min_max<BS>(mb, mn, unused_min, unused_max, sm4);
     if (threadIdx.x == 0) finish_pass(&srf, mb, mn);
     __syncthreads();
   }
@@ -1555,8 +1549,10 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
       first = false;
       if (pick < 0) break;
       last_pick = pick;
-      // the first slice of the pick's row is fetched before the barrier, so
-      // its global latency overlaps the side update below
+      // The pick's own key and side are updated by thread 0 while the other
+      // threads update its neighbours (never the pick itself: no self loops);
+      // the loop-top reads of this iteration all happened before the barrier
+      // above, so no barrier is needed between the two.
       const int32_t e0 = s_xadj[pick], e1 = s_xadj[pick + 1];
       const int32_t ef = e0 + (int32_t)threadIdx.x;
       int32_t y0 = 0;
@@ -1573,7 +1569,6 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
         s_key[pick] = cSide | (k & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
                       (k & 4095);
       }
-      __syncthreads();
       const int64_t room_next = room - bp;
       for (int32_t e = ef; e < e1; e += BS) {
         const int32_t y = e == ef ? y0 : lv.adj[e];
