@@ -1491,93 +1491,135 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
       s_key[v] = ((uint64_t)(s_gain[v] + (int64_t)cBias) << 12) | (uint64_t)(4095 - v);
     __syncthreads();
     auto vid = [](uint64_t k) { return (int32_t)(4095 - (int32_t)(k & 4095)); };
-    auto rescan_slots = [&](auto slots, int64_t room) {
+    // Best fitting key among the vertices of owner thread `own` (v = own mod
+    // BS), leaving out `skip`.  All slot loads are issued before any test,
+    // and the tests combine with bitwise operators, so a rescan costs one
+    // LDS round trip rather than a dependent load-and-branch per slot.
+    auto rescan_slots = [&](auto slots, int own, int64_t room, int32_t skip) {
       constexpr int S = decltype(slots)::value;
+      uint64_t kv[S];
+      int64_t bw[S];
+#pragma unroll
+      for (int q = 0; q < S; q++) {
+        const int32_t v = own + q * BS;
+        const int32_t vv = v < n ? v : 0;
+        kv[q] = s_key[vv];
+        bw[q] = s_b[vv];
+      }
       uint64_t bk = 0;
 #pragma unroll
       for (int q = 0; q < S; q++) {
-        const int32_t v = (int32_t)threadIdx.x + q * BS;
-        const int32_t vv = v < n ? v : 0;
-        const uint64_t kv = s_key[vv];
-        const uint64_t k = (v < n && (kv >> 63) == 0 && s_b[vv] <= room) ? kv : 0;
+        const int32_t v = own + q * BS;
+        const bool ok = (v < n) & (v != skip) & ((kv[q] >> 63) == 0) & (bw[q] <= room);
+        const uint64_t k = ok ? kv[q] : 0;
         bk = k > bk ? k : bk;
       }
       return bk;
     };
     static_assert(kTrialLdsMax <= 12 * BS, "slot classes cover the LDS-resident sizes");
-    auto rescan = [&](int64_t room) {
-      if (n <= 4 * BS) return rescan_slots(LaneXor<4>{}, room);
-      if (n <= 8 * BS) return rescan_slots(LaneXor<8>{}, room);
-      return rescan_slots(LaneXor<12>{}, room);
+    auto rescan = [&](int own, int64_t room, int32_t skip) {
+      if (n <= 4 * BS) return rescan_slots(LaneXor<4>{}, own, room, skip);
+      if (n <= 8 * BS) return rescan_slots(LaneXor<8>{}, own, room, skip);
+      return rescan_slots(LaneXor<12>{}, own, room, skip);
     };
-    s_best[threadIdx.x] = rescan(mg);
+    // s_best[t]: thread t's best, written by t at the loop top or, for the
+    // owner of the pick, by a rescanning lane of another wave while the
+    // update runs.  s_raise[t]: keys raised by the update (LDS atomicMax),
+    // folded into the best and cleared by t at the loop top.
+    __shared__ uint64_t s_raise[BS];
+    s_best[threadIdx.x] = rescan((int)threadIdx.x, mg, -1);
+    s_raise[threadIdx.x] = 0;
     __syncthreads();
     bool first = true;
-    int32_t last_pick = -1;
-    uint64_t seen = 0;     // the owner's best as of its last check
+    const bool seed_fits = s_b[seedv] <= mg;  // the first pick is the seed when it fits
+    const int seed_wave = (seedv % BS) / 64;
+    constexpr int kPre = 2;                    // row entries per lane fetched ahead
+    uint64_t seen = 0;     // the best as of its last fit check
     int64_t seen_b = 0;    // and that vertex's balance weight
     while (pg < tg) {
       const int64_t room = mg - pg;
       uint64_t bk = s_best[threadIdx.x];
+      const uint64_t rz = s_raise[threadIdx.x];
+      if (rz) {
+        s_raise[threadIdx.x] = 0;
+        bk = rz > bk ? rz : bk;
+      }
       if (bk != 0) {
-        // only the last pick changed side; only the best's weight can stop
-        // fitting, and it is reloaded only when the best changed
-        const int32_t bv = vid(bk);
+        // keys of unpicked vertices only grow and the room only shrinks, so
+        // the best needs a rescan only when its own weight stops fitting
         if (bk != seen) {
           seen = bk;
-          seen_b = s_b[bv];
+          seen_b = s_b[vid(bk)];
         }
-        if (bv == last_pick || seen_b > room) {
-          bk = rescan(room);
-          s_best[threadIdx.x] = bk;
+        if (seen_b > room) {
+          bk = rescan((int)threadIdx.x, room, -1);
           seen = bk;
           seen_b = bk ? s_b[vid(bk)] : 0;
         }
       }
+      s_best[threadIdx.x] = bk;
       uint64_t wk = bk;
       butterfly<64>([&](auto o) {
         const uint64_t k2 = xor_lane<decltype(o)::value>(wk);
         wk = k2 > wk ? k2 : wk;
       });
-      if (lane_id() == 0) s_wmax[threadIdx.x / 64] = wk;
+      // The pick is always one wave's best (or, first, the seed), so each
+      // wave fetches the row of its own candidate now and the global latency
+      // runs under the barrier; the wave whose candidate is picked applies
+      // the update from registers.  Candidates of different waves are
+      // different vertices (every vertex has one owner thread).
+      const int wave = (int)threadIdx.x / 64;
+      const int32_t pre = (first && seed_fits && wave == seed_wave) ? seedv : (wk ? vid(wk) : -1);
+      int32_t p0 = 0, p1 = 0;
+      int32_t py[kPre];
+      int64_t pw[kPre];
+      if (pre >= 0) {
+        p0 = s_xadj[pre];
+        p1 = s_xadj[pre + 1];
+#pragma unroll
+        for (int j = 0; j < kPre; j++) {
+          const int32_t e = p0 + lane_id() + 64 * j;
+          py[j] = e < p1 ? lv.adj[e] : 0;
+          pw[j] = e < p1 ? lv.w[e] : 0;
+        }
+      }
+      if (lane_id() == 0) s_wmax[wave] = wk;
       __syncthreads();
       uint64_t gk = s_wmax[0];
 #pragma unroll
       for (int w = 1; w < BS / 64; w++) gk = s_wmax[w] > gk ? s_wmax[w] : gk;
       int32_t pick = gk ? vid(gk) : -1;
-      if (first && pg + s_b[seedv] <= mg) pick = seedv;
+      if (first && seed_fits) pick = seedv;
       first = false;
       if (pick < 0) break;
-      last_pick = pick;
-      // The pick's own key and side are updated by thread 0 while the other
-      // threads update its neighbours (never the pick itself: no self loops);
-      // the loop-top reads of this iteration all happened before the barrier
-      // above, so no barrier is needed between the two.
-      const int32_t e0 = s_xadj[pick], e1 = s_xadj[pick + 1];
-      const int32_t ef = e0 + (int32_t)threadIdx.x;
-      int32_t y0 = 0;
-      int64_t w0 = 0;
-      if (ef < e1) {
-        y0 = lv.adj[ef];
-        w0 = lv.w[ef];
-      }
       const int64_t bp = s_b[pick];
-      if (threadIdx.x == 0) {
-        s_part[pick] = (int8_t)gs;
-        const uint64_t k = s_key[pick];
-        const int64_t f = (int64_t)((k & cField) >> 12);  // gain + 2^49
-        s_key[pick] = cSide | (k & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
-                      (k & 4095);
-      }
       const int64_t room_next = room - bp;
-      for (int32_t e = ef; e < e1; e += BS) {
-        const int32_t y = e == ef ? y0 : lv.adj[e];
-        const int64_t w = e == ef ? w0 : lv.w[e];
+      // the pick's owner gets a new best from a lane of the next wave, in
+      // parallel with the update (which runs in the owner's wave); a key it
+      // reads before the update raised it reaches s_raise as well
+      const int own = pick % BS;
+      if ((int)threadIdx.x == (own + 64) % BS) s_best[own] = rescan(own, room_next, pick);
+      auto apply = [&](int32_t y, int64_t w) {
         const uint64_t ky = s_key[y];
         const bool side = (ky >> 63) != 0;
         const uint64_t nk = (ky + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
         s_key[y] = nk;
-        if (!side && s_b[y] <= room_next) atomicMax((unsigned long long*)&s_best[y % BS], nk);
+        if (!side && s_b[y] <= room_next) atomicMax((unsigned long long*)&s_raise[y % BS], nk);
+      };
+      if (pre == pick) {
+        // lane 0 moves the pick itself while the other lanes update its
+        // neighbours (never the pick: no self loops)
+        if (lane_id() == 0) {
+          s_part[pick] = (int8_t)gs;
+          const uint64_t k = s_key[pick];
+          const int64_t f = (int64_t)((k & cField) >> 12);  // gain + 2^49
+          s_key[pick] = cSide | (k & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
+                        (k & 4095);
+        }
+#pragma unroll
+        for (int j = 0; j < kPre; j++)
+          if (p0 + lane_id() + 64 * j < p1) apply(py[j], pw[j]);
+        for (int32_t e = p0 + lane_id() + 64 * kPre; e < p1; e += 64) apply(lv.adj[e], lv.w[e]);
       }
       pg += bp;
       __syncthreads();
@@ -1598,14 +1640,22 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     // once (slots past n read vertex 0 and are discarded).
     auto rescan_slots = [&](auto slots, int64_t room, uint64_t& bk, int32_t& bv) {
       constexpr int S = decltype(slots)::value;
+      uint64_t kv[S];
+      int64_t bw[S];
+#pragma unroll
+      for (int q = 0; q < S; q++) {
+        const int32_t v = (int32_t)threadIdx.x + q * BS;
+        const int32_t vv = v < n ? v : 0;
+        kv[q] = s_key[vv];
+        bw[q] = s_b[vv];
+      }
       bk = 0;
       bv = -1;
 #pragma unroll
       for (int q = 0; q < S; q++) {
         const int32_t v = (int32_t)threadIdx.x + q * BS;
-        const int32_t vv = v < n ? v : 0;
-        const uint64_t kv = s_key[vv];
-        const uint64_t k = (v < n && (kv >> 63) == 0 && s_b[vv] <= room) ? kv : 0;
+        const bool ok = (v < n) & ((kv[q] >> 63) == 0) & (bw[q] <= room);
+        const uint64_t k = ok ? kv[q] : 0;
         const bool take = k > bk;  // ascending ids: ties keep the smaller id
         bk = take ? k : bk;
         bv = take ? v : bv;
