@@ -1,14 +1,17 @@
 // gp_kernels.hip - gfx950 kernels of the single-graph path and their launchers.
 //
 // Per level of the multilevel hierarchy:
-//   matching    k_match_propose / k_match_resolve (R rounds), k_hub,
-//               k_twohop, k_iso_count / k_iso_list / k_iso_pair
+//   matching    k_match_round (R rounds, each settling the previous one),
+//               k_match_settle, k_hub, k_twohop, k_iso_count / k_iso_list /
+//               k_iso_pair
 //   contraction k_contract_count -> k_contract_map -> k_contract_rows
 //               -> k_contract_long -> k_contract_compact
 // at the coarsest level
 //   initial bisection k_init_tot -> k_init_trials_lds (one trial per block)
 // per level on the way back up
-//   k_project, then P x (k_refine_gain -> k_refine_apply)
+//   k_project, then P x (k_refine_gain -> k_refine_settle) on levels of at
+//   most 65,536 vertices, P x (k_refine_gain -> k_refine_decide ->
+//   k_refine_apply -> k_refine_finish) on larger ones
 // and once at level 0 k_final_stats.  gp_create's checks: k_val_*, k_sort_*.
 // The kernels are thin wrappers of the bodies in gp_phases.h.
 #include <stdlib.h>
@@ -172,6 +175,14 @@ __global__ __launch_bounds__(kBlock) void k_refine_apply(int8_t* part, RefCtl* r
 }
 
 __global__ void k_refine_finish(RefCtl* rc, int32_t* pass_out) { b_refine_finish(rc, pass_out); }
+
+__global__ __launch_bounds__(kBlock) void k_refine_settle(int32_t n, int8_t* part, RefCtl* rc,
+                                                          const Cand* list,
+                                                          const int64_t* partials, int nparts,
+                                                          int32_t* pass_out) {
+  __shared__ SelShared sel;
+  b_refine_settle(n, part, rc, list, partials, nparts, &sel, pass_out);
+}
 
 __global__ __launch_bounds__(kBlock) void k_project(int32_t n, const int32_t* cmap,
                                                     const int8_t* cpart, int8_t* part, RefCtl* rc,
@@ -512,16 +523,16 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   return true;
 }
 
+// the gain launch; *grid_out = its block count (the number of partials)
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
-                    int64_t* partials, hipStream_t s) {
+                    int64_t* partials, int* grid_out, hipStream_t s) {
   // one row per team: the row loads of all vertices are in flight at once
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
   k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
   KCHECK();
-  k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
-  KCHECK();
+  *grid_out = grid;
   return true;
 }
 
@@ -529,14 +540,24 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
                         int64_t* partials, int tw,
                         int32_t* pass_out, hipStream_t s) {
   bool ok;
+  int grid = 0;
   switch (tw) {
-    case 4: ok = gain_tw<4>(lv, part, rc, list, partials, s); break;
-    case 8: ok = gain_tw<8>(lv, part, rc, list, partials, s); break;
-    case 16: ok = gain_tw<16>(lv, part, rc, list, partials, s); break;
-    case 32: ok = gain_tw<32>(lv, part, rc, list, partials, s); break;
-    default: ok = gain_tw<64>(lv, part, rc, list, partials, s); break;
+    case 4: ok = gain_tw<4>(lv, part, rc, list, partials, &grid, s); break;
+    case 8: ok = gain_tw<8>(lv, part, rc, list, partials, &grid, s); break;
+    case 16: ok = gain_tw<16>(lv, part, rc, list, partials, &grid, s); break;
+    case 32: ok = gain_tw<32>(lv, part, rc, list, partials, &grid, s); break;
+    default: ok = gain_tw<64>(lv, part, rc, list, partials, &grid, s); break;
   }
   if (!ok) return false;
+  if (lv.n <= kSettleMax) {
+    // decision, moves and pass bookkeeping in one single-block launch
+    ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
+    k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out);
+    KCHECK();
+    return true;
+  }
+  k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
+  KCHECK();
   {
     ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
     k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list, pass_out);

@@ -987,6 +987,51 @@ __device__ __forceinline__ void b_refine_decide(int32_t n, RefCtl* rc, const Can
   refine_decide_common(n, rc, list, sel, mode, s, ext_acc, cb, gmn, gmx);
 }
 
+// One block for a level of at most kSettleMax vertices: reduce the gain
+// launch's partials, decide, move the admitted candidates and close the pass,
+// all in the launch that follows the gain kernel (the candidate list holds at
+// most n entries, so one block walks it quickly).
+constexpr int32_t kSettleMax = 65536;
+
+__device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl* rc,
+                                                const Cand* list, const int64_t* partials,
+                                                int nparts, SelShared* sel, int32_t* pass_out) {
+  __shared__ int64_t sms[kBlock / 64];
+  if (rc->done) return;
+  b_refine_decide(n, rc, list, partials, nparts, sel);
+  __syncthreads();
+  const RefCtl r = *rc;
+  const int d = 1 - r.s;
+  int64_t mb = 0, mn = 0;
+  if (r.admit != kAdmitNone) {
+    const int64_t nc = r.ncand;
+    constexpr int U = 4;  // candidate loads in flight per thread
+    for (int64_t i0 = threadIdx.x; i0 < nc; i0 += (int64_t)U * kBlock) {
+      Cand c[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (i < nc) c[u] = list[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (i < nc && admitted(r, c[u])) {
+          part[c[u].v] = (int8_t)d;
+          mb += c[u].b;
+          mn++;
+        }
+      }
+    }
+  }
+  mb = block_sum<kBlock, int64_t>(mb, sms);
+  mn = block_sum<kBlock, int64_t>(mn, sms);
+  if (threadIdx.x == 0) {
+    finish_pass(rc, mb, mn);
+    *pass_out = rc->pass;
+  }
+}
+
 __device__ __forceinline__ void b_refine_finish(RefCtl* rc, int32_t* pass_out) {
   if (rc->done) return;
   if (threadIdx.x == 0) {
