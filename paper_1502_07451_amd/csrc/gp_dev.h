@@ -338,24 +338,39 @@ __device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int 
     sh->done = 0;
     sh->result = 0;
   }
+  // U candidates per thread are loaded before any is used, so that the
+  // loads of one round overlap instead of paying a round trip each; up to
+  // BS * U candidates stay in registers for all digits
+  constexpr int U = 4;
+  const bool cached = cnt <= (uint32_t)(BS * U);
+  Cand cc[U];
+  bool cg[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const uint32_t i = (uint32_t)(u * BS) + threadIdx.x;
+    cc[u].b = 0;
+    cg[u] = cached && i < cnt && items.get(i, cc[u]);
+  }
   __syncthreads();
   for (int d = ndig - 1; d >= 0; d--) {
     const int shf = 8 * d;
     for (int q = threadIdx.x; q < 256; q += BS) sh->hist[q] = 0;
     __syncthreads();
     const u128 P = sh->prefix;
-    // uniform trip count: every lane of a wave takes part in the ballots;
-    // U candidates per thread are loaded before any is used, so that the
-    // loads of one round overlap instead of paying a round trip each
-    constexpr int U = 4;
+    // uniform trip count: every lane of a wave takes part in the ballots
     for (uint32_t base = 0; base < cnt; base += BS * U) {
       Cand cs[U];
       bool got[U];
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        const uint32_t i = base + (uint32_t)(u * BS) + threadIdx.x;
-        cs[u].b = 0;
-        got[u] = i < cnt && items.get(i, cs[u]);
+        if (cached) {
+          cs[u] = cc[u];
+          got[u] = cg[u];
+        } else {
+          const uint32_t i = base + (uint32_t)(u * BS) + threadIdx.x;
+          cs[u].b = 0;
+          got[u] = i < cnt && items.get(i, cs[u]);
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; u++) {

@@ -200,7 +200,7 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
     ProfRec& r = g->prof.recs[i];
     if (r.level != level) continue;
     if (coarsening && (r.kind == PK_MATCH_PROPOSE || r.kind == PK_MATCH_RESOLVE))
-      r.executed = (r.idx == 0 || h.made[r.idx - 1] > 0) ? 1 : 0;
+      r.executed = (r.idx <= 1 || h.made[r.idx - 1] > 0) ? 1 : 0;
     if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_APPLY))
       r.executed = r.idx < h.lvl_pass[level] ? 1 : 0;
   }

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_match_resolve(int32_t n, int32_t* ma
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_match_round(LevelView lv, int32_t* match,
                                                         const int32_t* prop_prev,
-                                                        int32_t* prop_cur, const Ctrl* ctrl,
+                                                        int32_t* prop_cur, Ctrl* ctrl,
                                                         int round, uint64_t hs) {
   b_match_round<TW>(lv, match, prop_prev, prop_cur, ctrl, round, hs, (int)blockIdx.x,
                     (int)gridDim.x);
@@ -366,7 +366,7 @@ static bool propose_tw(const LevelView& lv, const int32_t* match, int32_t* prop,
 
 template <int TW>
 static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t* pb,
-                      const Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
+                      Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
   const double n = lv.n, m2 = lv.nnz;
   for (int r = 0; r < R; r++) {
@@ -378,7 +378,7 @@ static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t*
 }
 
 bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
-                         const Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s) {
+                         Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s) {
   if (R <= 0) return true;
   switch (tw) {
     case 4: rounds_tw<4>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
@@ -606,7 +606,7 @@ bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, cons
                  int8_t* out_part, hipStream_t s) {
   {
     ProfScope ps(PK_INIT_TOT, 0, 0.0, s);
-    k_init_tot<<<grid_for(lv.n, kBlock), kBlock, 0, s>>>(lv, is.tot);
+    k_init_tot<<<grid_for((int64_t)lv.n * kInitTotTeam, kBlock), kBlock, 0, s>>>(lv, is.tot);
   }
   KCHECK();
   // each of the K trials reads the coarsest graph once (xadj, adj + w, b,

@@ -72,7 +72,7 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s);
 // R matching rounds, each settling the previous one, then the last settled;
 // prop_a / prop_b: two int32[n] proposal buffers
 bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
-                         const Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s);
+                         Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s);
 bool launch_match_round(const LevelView& lv, int32_t* match, int32_t* prop, Ctrl* ctrl, int round,
                         uint64_t hs, int tw, hipStream_t s);
 bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratch& sc,

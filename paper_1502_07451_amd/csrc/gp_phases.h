@@ -133,9 +133,16 @@ __device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
 template <int TW>
 __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
                                               const int32_t* prop_prev, int32_t* prop_cur,
-                                              const Ctrl* ctrl, int round, uint64_t hs,
+                                              Ctrl* ctrl, int round, uint64_t hs,
                                               int bid_, int nblk_) {
+  // When settling round r - 1 matched nothing, round r proposed exactly what
+  // round r - 1 did (same free vertices, same rule), so it has no mutual
+  // pair either and every later round repeats it: those rounds return at
+  // once.  Both proposal buffers then hold the same proposals, so the final
+  // settle reads either.  made[r] = 1 records that round r's settle matched.
+  if (round >= 2 && ctrl->made[round - 1] == 0) return;
   const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
+  bool settled = false;
   const int lane = threadIdx.x & (TW - 1);
   const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
@@ -148,6 +155,7 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
         const int32_t p = prop_prev[u];
         if (p >= 0 && prop_prev[p] == u) {
           mu = p;
+          settled = true;
           if (lane == 0) match[u] = p;
         }
       }
@@ -187,6 +195,7 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
     });
     if (lane == 0) prop_cur[u] = bv;
   }
+  if (round >= 1 && __syncthreads_or(settled) && threadIdx.x == 0) ctrl->made[round] = 1;
 }
 
 // settles the mutual proposals of the last round
@@ -974,11 +983,24 @@ __device__ __forceinline__ void b_refine_decide(int32_t n, RefCtl* rc, const Can
   int mode, s;
   plan_pass(*rc, &mode, &s);
   int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
-    ext_acc += partials[4 * i + 0];
-    cb += partials[4 * i + 1];
-    gmn = partials[4 * i + 2] < gmn ? partials[4 * i + 2] : gmn;
-    gmx = partials[4 * i + 3] > gmx ? partials[4 * i + 3] : gmx;
+  // four partials per thread in flight
+  constexpr int U = 4;
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += U * kBlock) {
+    int64_t q[U][4];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int i = i0 + u * kBlock;
+#pragma unroll
+      for (int k = 0; k < 4; k++) q[u][k] = i < nparts ? partials[4 * i + k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (i0 + u * kBlock >= nparts) continue;
+      ext_acc += q[u][0];
+      cb += q[u][1];
+      gmn = q[u][2] < gmn ? q[u][2] : gmn;
+      gmx = q[u][3] > gmx ? q[u][3] : gmx;
+    }
   }
   ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
   cb = block_sum<kBlock, int64_t>(cb, sml);
@@ -1166,12 +1188,20 @@ __device__ __forceinline__ void b_clear_stats(Ctrl* ctrl, int bid_, int nblk_) {
 }
 
 // ------------------------------------------------------- initial bisection
+// tot[v] = sum of v's incident weights; one kInitTotTeam-lane team per row
+constexpr int kInitTotTeam = 16;
+
 __device__ __forceinline__ void b_init_tot(LevelView lv, int64_t* tot, int bid_, int nblk_) {
-  for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < lv.n;
-       v += (int64_t)nblk_ * kBlock) {
+  constexpr int TW = kInitTotTeam;
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t v = team; v < lv.n; v += nteams) {
     int64_t s = 0;
-    for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) s += lv.w[e];
-    tot[v] = s;
+    const int32_t e1 = lv.xadj[v + 1];
+    for (int32_t e = lv.xadj[v] + lane; e < e1; e += TW) s += lv.w[e];
+    s = team_sum<TW>(s);
+    if (lane == 0) tot[v] = s;
   }
 }
 
