@@ -313,3 +313,33 @@ def test_concurrent_streams_match_serial(gp):
                 assert r.cut == ref.cut and (r.load[0], r.load[1]) == ref.load
     for h in hs:
         h.close()
+
+
+def star_forest(sizes, rng, name):
+    """Stars (centre + leaves) joined by a few random edges, random weights:
+    matching stalls after the first rounds, the two-hop pass pairs the
+    leftover leaves."""
+    src, dst, n = [], [], 0
+    for k in sizes:
+        src += [n] * k
+        dst += list(range(n + 1, n + 1 + k))
+        n += k + 1
+    # a few edges between random vertices keep the cut from being zero
+    extra = rng.integers(0, n, (n // 6, 2))
+    extra = extra[extra[:, 0] != extra[:, 1]]
+    src = np.concatenate([np.asarray(src, np.int32), extra[:, 0].astype(np.int32)])
+    dst = np.concatenate([np.asarray(dst, np.int32), extra[:, 1].astype(np.int32)])
+    w = rng.integers(1, 100, len(src)).astype(np.int64)
+    vw = rng.integers(1, 20, (n, 2)).astype(np.int64)
+    return dagen.to_csr(n, src, dst, w, vw, name)
+
+
+@pytest.mark.parametrize("rounds", [2, 3, 8])
+def test_matching_stalls_match_oracle(gp, rounds):
+    # rounds after a settle that matched nothing return at once; every level's
+    # matching must still equal the oracle's
+    rng = np.random.default_rng(40 + rounds)
+    sizes = rng.integers(1, 60, 700).tolist() + [3000, 1]
+    g = star_forest(sizes, rng, "stars")
+    check_hierarchy(gp, g, coarsen_to=32, match_rounds=rounds)
+    assert_same(*run_both(gp, g, coarsen_to=32, match_rounds=rounds))
