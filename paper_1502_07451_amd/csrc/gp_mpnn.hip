@@ -190,8 +190,20 @@ __global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const int64
   for (int32_t v = threadIdx.x; v < n; v += kBlock) {
     int64_t g = 0;
     const int8_t pv = s_part[v];
-    for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++)
-      g += s_part[lv.adj[e]] != pv ? lv.w[e] : -lv.w[e];
+    constexpr int U = 8;  // row entries in flight per thread
+    const int32_t e1 = lv.xadj[v + 1];
+    for (int32_t e = lv.xadj[v]; e < e1; e += U) {
+      int32_t y[U];
+      int64_t w[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        y[u] = e + u < e1 ? lv.adj[e + u] : 0;
+        w[u] = e + u < e1 ? lv.w[e + u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (e + u < e1) g += s_part[y[u]] != pv ? w[u] : -w[u];
+    }
     s_gain[v] = g;
   }
   if (threadIdx.x == 0) {

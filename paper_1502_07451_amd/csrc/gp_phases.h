@@ -1478,13 +1478,25 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
       }
     }
     __syncthreads();
+    // neighbours of the moved vertices: U row entries per thread in flight,
+    // so a row costs a few global round trips rather than one per entry
     for (int32_t v = threadIdx.x; v < n; v += BS)
       if (s_mv[v]) {
-        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
-          const int32_t y = lv.adj[e];
-          const int64_t w = lv.w[e];
-          atomicAdd((unsigned long long*)&s_gain[y],
-                    (unsigned long long)(s_part[y] == d ? -2 * w : 2 * w));
+        constexpr int U = 8;
+        const int32_t e1 = lv.xadj[v + 1];
+        for (int32_t e = lv.xadj[v]; e < e1; e += U) {
+          int32_t y[U];
+          int64_t w[U];
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            y[u] = e + u < e1 ? lv.adj[e + u] : 0;
+            w[u] = e + u < e1 ? lv.w[e + u] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            if (e + u < e1)
+              atomicAdd((unsigned long long*)&s_gain[y[u]],
+                        (unsigned long long)(s_part[y[u]] == d ? -2 * w[u] : 2 * w[u]));
         }
         s_mv[v] = 0;
       }
