@@ -1681,11 +1681,23 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
       if (pick < 0) break;
       const int64_t bp = s_b[pick];
       const int64_t room_next = room - bp;
-      // the pick's owner gets a new best from a lane of the next wave, in
-      // parallel with the update (which runs in the owner's wave); a key it
-      // reads before the update raised it reaches s_raise as well
+      // the pick's owner gets a new best from 16 lanes of the next wave (one
+      // slot each, then a 16-lane maximum), in parallel with the update,
+      // which runs in the owner's wave; a key read before the update raised
+      // it reaches s_raise as well
       const int own = pick % BS;
-      if ((int)threadIdx.x == (own + 64) % BS) s_best[own] = rescan(own, room_next, pick);
+      static_assert(kTrialLdsMax <= 16 * BS, "one rescanning lane per slot");
+      if (wave == ((own + 64) % BS) / 64 && lane_id() < 16) {
+        const int32_t v = own + lane_id() * BS;
+        uint64_t k = 0;
+        if (v < n && v != pick) {
+          const uint64_t kv = s_key[v];
+          const int64_t bv = s_b[v];
+          k = ((kv >> 63) == 0 && bv <= room_next) ? kv : 0;
+        }
+        k = team_max<16>(k);
+        if (lane_id() == 0) s_best[own] = k;
+      }
       auto apply = [&](int32_t y, int64_t w) {
         const uint64_t ky = s_key[y];
         const bool side = (ky >> 63) != 0;
