@@ -1706,18 +1706,34 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
         if (!side && s_b[y] <= room_next) atomicMax((unsigned long long*)&s_raise[y % BS], nk);
       };
       if (pre == pick) {
-        // lane 0 moves the pick itself while the other lanes update its
-        // neighbours (never the pick: no self loops)
+        // lane 0 moves the pick itself while the lanes update its neighbours
+        // (never the pick: no self loops); every LDS read is issued before
+        // any write, so the update is one round trip
+        uint64_t ky[kPre];
+        int64_t by[kPre];
+#pragma unroll
+        for (int j = 0; j < kPre; j++) {
+          const bool act = p0 + lane_id() + 64 * j < p1;
+          ky[j] = act ? s_key[py[j]] : 0;
+          by[j] = act ? s_b[py[j]] : 0;
+        }
+        const uint64_t kp = lane_id() == 0 ? s_key[pick] : 0;
+#pragma unroll
+        for (int j = 0; j < kPre; j++) {
+          if (p0 + lane_id() + 64 * j >= p1) continue;
+          const bool side = (ky[j] >> 63) != 0;
+          const int64_t w = pw[j];
+          const uint64_t nk = (ky[j] + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
+          s_key[py[j]] = nk;
+          if (!side && by[j] <= room_next)
+            atomicMax((unsigned long long*)&s_raise[py[j] % BS], nk);
+        }
         if (lane_id() == 0) {
           s_part[pick] = (int8_t)gs;
-          const uint64_t k = s_key[pick];
-          const int64_t f = (int64_t)((k & cField) >> 12);  // gain + 2^49
-          s_key[pick] = cSide | (k & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
-                        (k & 4095);
+          const int64_t f = (int64_t)((kp & cField) >> 12);  // gain + 2^49
+          s_key[pick] = cSide | (kp & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
+                        (kp & 4095);
         }
-#pragma unroll
-        for (int j = 0; j < kPre; j++)
-          if (p0 + lane_id() + 64 * j < p1) apply(py[j], pw[j]);
         for (int32_t e = p0 + lane_id() + 64 * kPre; e < p1; e += 64) apply(lv.adj[e], lv.w[e]);
       }
       pg += bp;
