@@ -322,10 +322,91 @@ struct LdsItems {
 // their sum with one atomic, which keeps skewed digits from serialising on
 // one bin), then a block-wide scan over the bins from the top picks the bin
 // where the bound is crossed.
+// Exact threshold of select_prefix (below) for at most kSelSmall
+// candidates.  They are gathered into LDS; thread i takes candidate i and
+// sums the weights of the candidates whose keys are larger (keys are
+// distinct), which gives its running sum in the order key desc; the one
+// candidate whose running sum first reaches the bound is the crossing one.
+// The result equals the radix descent's:
+//   want_ge: bound <= 0 -> the all-ones key of the digit width; total < bound
+//            -> 0; else the key at which the running sum first reaches bound;
+//   else:    bound < 0 -> that all-ones key + 1; total <= bound -> 0; else the
+//            key at which the running sum first exceeds bound, + 1.
+constexpr int kSelSmall = 256;
+
+template <int BS, class Items>
+__device__ u128 select_small(const Items& items, int64_t gmin, int idbits, int tbits, int want_ge,
+                             int64_t bound, SelShared* sh) {
+  // key words interleaved (one 16-byte read per key), padded to a multiple
+  // of 8 with key 0 and weight 0, which change no running sum
+  __shared__ __align__(16) uint64_t s_key[2 * kSelSmall];
+  __shared__ int64_t s_w[kSelSmall];
+  __shared__ int s_cnt;
+  const int ndig = (tbits + 7) / 8;
+  const u128 ones = (((u128)1) << (8 * ndig)) - 1;
+  if (want_ge ? bound <= 0 : bound < 0) return want_ge ? ones : ones + 1;
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    sh->result = 0;  // the running sums never reach the bound
+  }
+  for (int i = threadIdx.x; i < kSelSmall; i += BS) {
+    s_key[2 * i] = 0;
+    s_key[2 * i + 1] = 0;
+    s_w[i] = 0;
+  }
+  __syncthreads();
+  const uint32_t cnt = items.count();
+  for (uint32_t i = threadIdx.x; i < cnt; i += BS) {
+    Cand c;
+    if (!items.get(i, c)) continue;
+    const int slot = atomicAdd(&s_cnt, 1);
+    if (slot < kSelSmall) {
+      const u128 k = cand_key(c, gmin, idbits);
+      s_key[2 * slot] = (uint64_t)(k >> 64);
+      s_key[2 * slot + 1] = (uint64_t)k;
+      s_w[slot] = c.b;
+    }
+  }
+  __syncthreads();
+  const int m = s_cnt < kSelSmall ? s_cnt : kSelSmall;
+  const int m8 = (m + 7) & ~7;
+  for (int i = threadIdx.x; i < m; i += BS) {
+    const uint64_t hi = s_key[2 * i], lo = s_key[2 * i + 1];
+    const int64_t wi = s_w[i];
+    int64_t above = 0;  // weights of the larger keys
+    for (int j0 = 0; j0 < m8; j0 += 8) {
+      uint64_t hj[8], lj[8];
+      int64_t wj[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        hj[u] = s_key[2 * (j0 + u)];
+        lj[u] = s_key[2 * (j0 + u) + 1];
+        wj[u] = s_w[j0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        above += (hj[u] > hi || (hj[u] == hi && lj[u] > lo)) ? wj[u] : 0;
+    }
+    const int64_t incl = above + wi;
+    const bool cross = want_ge ? (incl >= bound && above < bound) : (incl > bound && above <= bound);
+    if (cross) {
+      const u128 k = ((u128)hi << 64) | (u128)lo;
+      sh->result = want_ge ? k : k + 1;
+    }
+  }
+  __syncthreads();
+  const u128 r = sh->result;
+  __syncthreads();
+  return r;
+}
+
 template <int BS, class Items>
 __device__ u128 select_prefix(const Items& items, int64_t gmin, int idbits, int tbits,
-                              int want_ge, int64_t bound, SelShared* sh) {
+                              int want_ge, int64_t bound, SelShared* sh,
+                              uint32_t ncand_hint = 0xffffffffu) {
   static_assert(BS % 64 == 0 && (BS >= 256 || 256 % BS == 0), "block of whole waves");
+  if (ncand_hint <= (uint32_t)kSelSmall)
+    return select_small<BS>(items, gmin, idbits, tbits, want_ge, bound, sh);
   constexpr int PER = BS >= 256 ? 1 : 256 / BS;  // histogram bins per thread
   __shared__ int64_t sm_scan[BS / 64];
   __shared__ int32_t sm_min[BS / 64];

@@ -823,13 +823,14 @@ __device__ void decide_admission(RefCtl* rc, const Items& items, uint32_t ncand,
     admit = kAdmitAll;
   } else {
     const int tbits = bitlen64((uint64_t)(gmax - gmin)) + idbits;
+    // ncand is the exact candidate count: small counts take the rank form
     if (mode == 0) {
-      thr = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh);
+      thr = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh, ncand);
     } else {
       const int64_t excess = rc->pw[s] - rc->maxw[s];
-      u128 t1 = select_prefix<BS>(items, gmin, idbits, tbits, 1, excess, sh);
+      u128 t1 = select_prefix<BS>(items, gmin, idbits, tbits, 1, excess, sh, ncand);
       u128 t2 = 0;
-      if (cand_b > budget) t2 = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh);
+      if (cand_b > budget) t2 = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh, ncand);
       thr = t1 > t2 ? t1 : t2;
     }
     admit = kAdmitThr;
