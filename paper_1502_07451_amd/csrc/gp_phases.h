@@ -148,16 +148,18 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
   for (int64_t uu = team; uu < lv.n; uu += nteams) {
     const int32_t u = (int32_t)uu;
+    // loads that do not depend on each other are issued together, before
+    // any test, so that each chain costs as few global round trips as it can
+    const int64_t bu = lv.b[u];
+    const int32_t e0 = lv.xadj[u], e1 = lv.xadj[u + 1];
     int32_t mu = -1;
     if (round > 0) {
       mu = match[u];
-      if (mu == -1) {
-        const int32_t p = prop_prev[u];
-        if (p >= 0 && prop_prev[p] == u) {
-          mu = p;
-          settled = true;
-          if (lane == 0) match[u] = p;
-        }
+      const int32_t p = prop_prev[u];
+      if (mu == -1 && p >= 0 && prop_prev[p] == u) {
+        mu = p;
+        settled = true;
+        if (lane == 0) match[u] = p;
       }
     } else if (lane == 0) {
       match[u] = -1;
@@ -166,20 +168,20 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
       if (lane == 0) prop_cur[u] = -1;
       continue;
     }
-    const int64_t bu = lv.b[u];
     const bool capcheck = bu + maxb > cap;
     int64_t bw = -1;
     int32_t bv = -1;
-    const int32_t e1 = lv.xadj[u + 1];
-    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
+    for (int32_t e = e0 + lane; e < e1; e += TW) {
       const int32_t v = lv.adj[e];
+      const int64_t w = lv.w[e];
+      const int64_t bv_v = capcheck ? lv.b[v] : 0;
       if (round > 0) {
-        if (match[v] != -1) continue;
+        const int32_t mv = match[v];
         const int32_t pv = prop_prev[v];
+        if (mv != -1) continue;
         if (pv >= 0 && prop_prev[pv] == v) continue;
       }
-      if (capcheck && bu + lv.b[v] > cap) continue;
-      const int64_t w = lv.w[e];
+      if (capcheck && bu + bv_v > cap) continue;
       if (match_better(w, v, bw, bv, hs, u)) {
         bw = w;
         bv = v;
