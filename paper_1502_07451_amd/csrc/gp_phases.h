@@ -1445,8 +1445,12 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
                            int8_t* s_part, int8_t* s_mv, RefCtl& srf, SelShared& sel) {
   const int32_t n = lv.n;
   __shared__ int64_t sm4[4 * (BS / 64)];
+  constexpr int kChunk = 16, kChunkCap = 512;
+  __shared__ int32_t s_chunk_v[kChunkCap], s_chunk_e[kChunkCap];
+  __shared__ int s_nchunk;
   for (;;) {
     if (srf.done) break;
+    if (threadIdx.x == 0) s_nchunk = 0;
     int mode, s;
     plan_pass(srf, &mode, &s);
     const LdsItems items{s_gain, s_b, s_part, n, s, mode};
@@ -1467,7 +1471,8 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
     __syncthreads();
     decide_admission<BS>(&srf, items, (uint32_t)cnt, cb, gmn, gmx, n, &sel);
     __syncthreads();
-    // admitted vertices change side (each thread only touches its own)
+    // admitted vertices change side (each thread only touches its own) and
+    // queue their rows as chunks of kChunk entries
     const int d = 1 - s;
     int64_t mb = 0, mn = 0;
     for (int32_t v = threadIdx.x; v < n; v += BS) {
@@ -1478,12 +1483,40 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
         s_gain[v] = -c.gain;
         mb += c.b;
         mn++;
+        const int32_t a = lv.xadj[v], nc = (lv.xadj[v + 1] - a + kChunk - 1) / kChunk;
+        const int slot = atomicAdd(&s_nchunk, nc);
+        for (int k = 0; k < nc && slot + k < kChunkCap; k++) {
+          s_chunk_v[slot + k] = v;
+          s_chunk_e[slot + k] = a + k * kChunk;
+        }
       }
     }
     __syncthreads();
-    // neighbours of the moved vertices: U row entries per thread in flight,
-    // so a row costs a few global round trips rather than one per entry
-    for (int32_t v = threadIdx.x; v < n; v += BS)
+    const int nchunk = s_nchunk;
+    if (nchunk <= kChunkCap) {
+      // every thread takes whole chunks, kChunk loads in flight: the rows of
+      // all moved vertices cost about one global round trip together
+      for (int c = threadIdx.x; c < nchunk; c += BS) {
+        const int32_t v = s_chunk_v[c], e = s_chunk_e[c];
+        const int32_t e1 = lv.xadj[v + 1];
+        int32_t y[kChunk];
+        int64_t w[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; u++) {
+          y[u] = e + u < e1 ? lv.adj[e + u] : 0;
+          w[u] = e + u < e1 ? lv.w[e + u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; u++)
+          if (e + u < e1)
+            atomicAdd((unsigned long long*)&s_gain[y[u]],
+                      (unsigned long long)(s_part[y[u]] == d ? -2 * w[u] : 2 * w[u]));
+        if (e == lv.xadj[v]) s_mv[v] = 0;
+      }
+    }
+    // otherwise (a long queue): U row entries per thread in flight, one
+    // moved vertex per thread
+    for (int32_t v = threadIdx.x; v < n && nchunk > kChunkCap; v += BS)
       if (s_mv[v]) {
         constexpr int U = 8;
         const int32_t e1 = lv.xadj[v + 1];
