@@ -201,6 +201,10 @@ def main():
                 "kernel": dom_name, "avg_launch_us": round(avg_ms * 1e3, 3),
                 "alg_bytes_per_launch": round(bytes_per_launch),
                 "kernel_share_of_step": round(dom["ms"] / total_ms, 4)}
+    if dom_name == "k_init_trials":
+        # what bounds it: one vertex per step of a serial chain
+        roofline["limiter"] = ("serial greedy picks: dependent LDS round trips and two "
+                               "block barriers per pick, not HBM bandwidth")
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
