@@ -343,3 +343,32 @@ def test_matching_stalls_match_oracle(gp, rounds):
     g = star_forest(sizes, rng, "stars")
     check_hierarchy(gp, g, coarsen_to=32, match_rounds=rounds)
     assert_same(*run_both(gp, g, coarsen_to=32, match_rounds=rounds))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_mixed_sweep(gp, seed):
+    """50 mixed graphs (random, layered, tiled Cholesky, tiled LU) with random
+    options per seed: partition, cut, loads and level count as the oracle's."""
+    rng = np.random.default_rng(1000 + seed)
+    for case in range(50):
+        kind = int(rng.integers(0, 4))
+        if kind == 0:
+            g = random_graph(int(rng.integers(2, 3000)), float(rng.uniform(0.0005, 0.02)), rng,
+                             wmax=int(rng.choice([10, 10**6])), vmax=int(rng.choice([10, 10**4])))
+        elif kind == 1:
+            g = dagen.layered(int(rng.integers(500, 60000)), int(rng.integers(2, 40)),
+                              rate=int(rng.integers(1, 5)), seed=int(rng.integers(0, 10**6)))
+        elif kind == 2:
+            g = dagen.cholesky(int(rng.integers(4, 24)), 512, jitter_pm=100,
+                               seed=int(rng.integers(0, 10**6)))
+        else:
+            g = dagen.lu(int(rng.integers(4, 20)), 512, jitter_pm=100,
+                         seed=int(rng.integers(0, 10**6)))
+        kw = dict(ratio=(int(rng.integers(1, 6)), int(rng.integers(1, 6))),
+                  eps_ppm=int(rng.choice([0, 10000, 30000, 100000])),
+                  balance_on=int(rng.integers(0, 2)), coarsen_to=int(rng.choice([16, 64, 256, 2048])),
+                  match_rounds=int(rng.choice([1, 2, 3, 8])),
+                  refine_passes=int(rng.choice([1, 2, 8])),
+                  init_trials=int(rng.choice([1, 4, 16])), seed=int(rng.integers(0, 1000)))
+        ref, got, res, _ = run_both(gp, g, trace=False, **kw)
+        assert_same(ref, got, res)
