@@ -9,7 +9,7 @@
  * coarsest graph: a 3-layer message-passing network (hidden size 64, BF16
  * weights) scores every coarsest vertex; the highest scores fill the grown
  * side; the usual refinement follows; the plain greedy-growing result stays
- * the fallback and the judge.  The partition arithmetic stays integer: the
+ * the fallback and the yardstick.  The partition arithmetic stays integer: the
  * network only orders vertices.
  *
  * Inference is specified exactly, so that a CPU emulation reproduces the

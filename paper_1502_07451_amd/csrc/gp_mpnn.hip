@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_score(int32_t n, const uint16_t* 
   }
 }
 
-// Proposal, refinement and judge for the coarsest graph, one block.
+// Proposal, refinement and acceptance check for the coarsest graph, one block.
 // Phase 1 sorts (score key desc, id asc) in LDS and writes the order to
 // `order`; phase 2 fills the grown side, computes the gains of that
 // assignment, refines it and keeps it when strictly better than the plain
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const int64
     for (int i = threadIdx.x; i < n; i += kBlock) order[i] = (int32_t)(~(uint32_t)key[i]);
     __syncthreads();
   }
-  // ---- phase 2: fill, gains, refinement, judge
+  // ---- phase 2: fill, gains, refinement, acceptance check
   int64_t* s_gain = (int64_t*)lds;
   int64_t* s_b = s_gain + n;
   int8_t* s_part = (int8_t*)(s_b + n);

@@ -3,7 +3,7 @@
 The network (3 message-passing layers, hidden size 64, BF16 weights) scores
 the vertices of the coarsest graph; the proposal fills the grown side in
 score order and the exact refinement runs after it, while the plain
-greedy-growing bisection stays both the fallback and the judge.  It is
+greedy-growing bisection stays both the fallback and the yardstick.  It is
 trained on what the plain pipeline itself produces: every training DAG is
 partitioned by the batched GPU pipeline with the coarsest-level export on,
 and the label of a coarsest vertex is its side in the refined plain

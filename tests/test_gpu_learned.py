@@ -1,5 +1,5 @@
 """Learned coarsest-level proposal on the GPU vs the oracle: inference scores
-bit for bit, and whole partitions with the proposal and its judge."""
+bit for bit, and whole partitions with the proposal and its acceptance check."""
 import sys
 
 import numpy as np
@@ -75,7 +75,7 @@ def test_learned_requires_model(gp):
 
 def test_trained_weights_match_oracle(gp):
     """The committed trained weights: the learned path on the tiled Cholesky
-    T=64 DAG equals the oracle's, judge decision included."""
+    T=64 DAG equals the oracle's, acceptance decision included."""
     import os
     from paper_1502_07451_amd import learn
     if not os.path.exists(learn.WEIGHTS_PATH):
