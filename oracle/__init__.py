@@ -42,6 +42,8 @@ def _load():
     lib.or_balance.argtypes = [i64, i64, i64, i32, vp, vp]
     lib.or_balance.restype = None
     lib.or_canonicalize.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_mix64.restype = u64
+    lib.or_mix64.argtypes = [u64]
     lib.or_edge_hash.restype = u64
     lib.or_edge_hash.argtypes = [u64, i32, i32, i32]
     lib.or_match.restype = i64
@@ -62,6 +64,7 @@ def _load():
     lib.or_mpnn_scores.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
     lib.or_bf16_round.restype = ctypes.c_uint16
     lib.or_bf16_round.argtypes = [ctypes.c_float]
+    lib.or_learned_fill.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
     lib.or_mpnn_loss_grad_f64.restype = ctypes.c_double
     lib.or_mpnn_loss_grad_f64.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     _lib = lib
@@ -134,6 +137,11 @@ def canonicalize(n, xadj, adjncy, adjwgt, vwgt):
     rc = _load().or_canonicalize(n, _p(xadj), _p(adjncy), _p(adjwgt), _p(vwgt), _p(ox), _p(oa),
                                  _p(ow))
     return rc, ox, oa[:nnz], ow[:nnz]
+
+
+def mix64(z: int) -> int:
+    """The SplitMix64 output finaliser the matching hash is built from."""
+    return int(_load().or_mix64(z & (2**64 - 1)))
 
 
 def edge_hash(seed: int, level: int, a: int, b: int) -> int:
@@ -252,6 +260,20 @@ def mpnn_scores(g, params_bf16: np.ndarray) -> np.ndarray:
                                 _p(_c(g.adjwgt, np.int64)), _p(vc), _p(vg), _p(P), _p(out))
     assert rc == 0
     return out[:g.n]
+
+
+def learned_fill(g, params_bf16: np.ndarray, b, gs: int, tgt, maxw):
+    """The learned proposal before refinement: (part, pw)."""
+    P = _c(params_bf16, np.uint16)
+    assert P.size == mpnn_nparam()
+    part = np.zeros(max(g.n, 1), np.int8)
+    pw = np.zeros(2, np.int64)
+    rc = _load().or_learned_fill(g.n, _p(_c(g.xadj, np.int32)), _p(_c(g.adjncy, np.int32)),
+                                 _p(_c(g.adjwgt, np.int64)), _p(_c(g.vwgt[:, 0], np.int64)),
+                                 _p(_c(g.vwgt[:, 1], np.int64)), _p(_c(b, np.int64)), _p(P), gs,
+                                 _p(_c(tgt, np.int64)), _p(_c(maxw, np.int64)), _p(part), _p(pw))
+    assert rc == 0
+    return part[:g.n], pw
 
 
 def mpnn_loss_grad_f64(g, bw: np.ndarray, labels: np.ndarray, params: np.ndarray):

@@ -203,6 +203,22 @@ int or_learned_proposal(const OG* g, const int64_t* b, const void* model, int gs
   return 0;
 }
 
+/* The proposal alone on plain arrays (exported for tests): b is the balance
+ * column; the caller passes the grown side gs and the bounds. */
+int or_learned_fill(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                    const int64_t* vc, const int64_t* vg, const int64_t* b, const void* model,
+                    int32_t gs, const int64_t* tgt, const int64_t* maxw, int8_t* part,
+                    int64_t* pw) {
+  OG g;
+  g.n = n;
+  g.xadj = (int32_t*)xadj;
+  g.adj = (int32_t*)adj;
+  g.w = (int64_t*)w;
+  g.vc = (int64_t*)vc;
+  g.vg = (int64_t*)vg;
+  return or_learned_proposal(&g, b, model, gs, tgt, maxw, part, pw);
+}
+
 /* ------------------------------------------------------------------------ */
 /* FP64 reference of the training objective and its gradient.              */
 /* The same network without rounding (all FP64, weights as given).  Loss:   */

@@ -178,6 +178,10 @@ static uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+/* the finaliser alone (exported so tests can check it against the published */
+/* SplitMix64 outputs)                                                        */
+uint64_t or_mix64(uint64_t z) { return mix64(z); }
+
 uint64_t or_edge_hash(uint64_t seed, int32_t level, int32_t a, int32_t b) {
   int32_t lo = a < b ? a : b, hi = a < b ? b : a;
   uint64_t hs = mix64(seed ^ (uint64_t)(uint32_t)level);
