@@ -72,7 +72,7 @@ typedef struct {
   int32_t init_trials;   /* greedy-growing trials, [1, 64] (default 16) */
   int32_t flags;         /* GP_LEARNED | GP_TRACE | GP_HOST_PTRS (for part/res of batch calls) */
   int32_t reserved;
-  const void* model;     /* from gp_model_create; required iff GP_LEARNED */
+  const void* model;     /* from gp_model_create / gp_model_load; required iff GP_LEARNED */
 } gp_options;
 
 typedef struct {
@@ -125,7 +125,9 @@ gp_status gp_partition_trace(gp_graph* g, const gp_options* o, int8_t* part, gp_
  * and the final bisection of that level (n).  Every output may be NULL.
  * Blocks until the copies are done.  GP_EINVAL when no partition has run or
  * the level was not built by it.  For inspecting the multilevel hierarchy
- * (Section IV-C's coarsening); not needed to partition. */
+ * that the partition builds (the paper delegates partitioning to a
+ * multilevel library, Section III-A; the coarsening rules are this
+ * library's own); not needed to partition. */
 gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, int32_t* xadj,
                         int32_t* adjncy, int64_t* adjwgt, int64_t* vwgt, int32_t* match,
                         int8_t* part);
@@ -136,11 +138,19 @@ void gp_destroy(gp_graph* g);
  * network, hidden size 64, whose 25,153 BF16 parameters (uint16 bits, host
  * memory) are laid out as Win[64][4], b_in[64], 3 x (Ws[64][64], Wn[64][64],
  * b[64]), wo[64], bo (matrices [output][input]).  It scores the coarsest
- * vertices; the best fill the grown side; refinement follows; the plain
- * bisection is kept unless the learned one is strictly better in
- * (infeasible, cut).  It runs when the coarsest graph has at most 3,072
- * vertices.  *model is device state owned by the library. */
+ * vertices; the best fill the grown side; refinement follows.  Both that
+ * bisection and the plain one are projected and refined down to the input
+ * graph, and the plain result is kept unless the learned one ends strictly
+ * better there in (infeasible, cut), so the learned form never returns a
+ * larger cut than the plain one.  It runs when the coarsest graph has at
+ * most 3,072 vertices.  After such a call gp_level_read shows the levels of
+ * the learned run.  *model is device state owned by the library. */
 gp_status gp_model_create(const uint16_t* params, int32_t count, const void** model);
+/* As gp_model_create, with the blob read from a file holding exactly the
+ * 25,153 little-endian BF16 values in the order above (50,306 bytes, no
+ * header; what the training driver writes).  GP_EINVAL when the file cannot
+ * be opened, GP_EMODEL when its size differs; *model is then NULL. */
+gp_status gp_model_load(const char* path, const void** model);
 void gp_model_free(const void* model);
 /* The network's FP32 score of every vertex of g's graph (its canonical rows):
  * scores is float[n], device memory unless g was created with GP_HOST_PTRS. */

@@ -630,13 +630,51 @@ int or_init_bisect(int32_t n, const int32_t* xadj, const int32_t* adj, const int
 /*       [8] init trials K  [9] flags (bit 1: learned proposal)              */
 /* res:  [0] cut  [1..2] part weights (balance column)  [3] CPU time of part */
 /*       0 (cpu costs)  [4] GPU time of part 1 (gpu costs)  [5] feasible     */
-/*       [6] levels  [7] learned proposal kept                               */
+/*       [6] levels  [7] learned result kept (judged on the input graph)    */
 /* trace (optional, 8 int64 per level, level 0 first): n, nnz, passes,       */
 /*       moves, cut after refinement, pw0, pw1, pairs matched on this level  */
 /* Coarsening runs while n > C, and stops after a level that removed less   */
 /* than 5 % of the vertices (20 n' > 19 n) or after 48 levels; a stalled     */
 /* level is kept.  The matching weight cap is ceil(3W / (2C)).              */
 /* ------------------------------------------------------------------------ */
+/* Uncoarsening from the coarsest level L to level 0: project the bisection
+   to the finer level through cmap, then refine it there.  *partp holds the
+   coarsest level's bisection on entry (pw its part weights) and the level-0
+   bisection on return.  Writes the coarsest level's and every finer level's
+   trace row. */
+static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, const int64_t* pairs,
+                     const int64_t* maxw, int P, int8_t** partp, int64_t* pw, int64_t* trace,
+                     int32_t trace_cap) {
+  int8_t* part = *partp;
+  if (trace && L < trace_cap) {
+    OG* g = &lv[L];
+    int64_t* t = trace + 8 * L;
+    t[0] = g->n; t[1] = g->xadj[g->n]; t[2] = 0; t[3] = 0;
+    t[4] = or_cut(g->n, g->xadj, g->adj, g->w, part);
+    t[5] = pw[0]; t[6] = pw[1]; t[7] = pairs[L];
+  }
+  for (int l = L - 1; l >= 0; l--) {
+    OG* g = &lv[l];
+    const int64_t* b = bal ? g->vg : g->vc;
+    int8_t* next = (int8_t*)malloc((size_t)(g->n > 0 ? g->n : 1));
+    if (!next) { *partp = part; return OR_ENOMEM; }
+    for (int32_t u = 0; u < g->n; u++) next[u] = part[cmap[l][u]];
+    free(part);
+    part = next;
+    int64_t moves = 0;
+    int passes = refine_og(g, b, part, pw, maxw, P, &moves);
+    if (passes < 0) { *partp = part; return OR_ENOMEM; }
+    if (trace && l < trace_cap) {
+      int64_t* t = trace + 8 * l;
+      t[0] = g->n; t[1] = g->xadj[g->n]; t[2] = passes; t[3] = moves;
+      t[4] = or_cut(g->n, g->xadj, g->adj, g->w, part);
+      t[5] = pw[0]; t[6] = pw[1]; t[7] = pairs[l];
+    }
+  }
+  *partp = part;
+  return OR_OK;
+}
+
 #define OR_FLAG_LEARNED 2
 
 int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
@@ -689,63 +727,58 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
     if (20 * (int64_t)lv[L].n > 19 * (int64_t)lv[L - 1].n || L == OR_MAX_LEVELS) break;
   }
   int8_t* part = NULL;
-  int8_t* next = NULL;
+  int8_t* lp = NULL;
   int64_t pw[2] = {0, 0};
+  int64_t lpw[2] = {0, 0};
   int used_learned = 0;
+  int64_t* ltrace = NULL;
   if (rc == OR_OK) {
     OG* g = &lv[L];
     const int64_t* b = bal ? g->vg : g->vc;
     part = (int8_t*)malloc((size_t)(g->n > 0 ? g->n : 1));
     if (!part) rc = OR_ENOMEM;
     if (rc == OR_OK) rc = init_bisect_og(g, b, r0, r1, tgt, maxw, (int)K, (int)P, part, pw);
-    /* the learned proposal runs on coarsest graphs of at most 3,072 vertices */
+    /* the learned proposal runs on coarsest graphs of at most 3,072 vertices;
+       its refined bisection is carried through the uncoarsening beside the
+       plain one (below) */
     if (rc == OR_OK && (flags & OR_FLAG_LEARNED) && g->n > 0 && g->n <= 3072) {
-      int8_t* lp = (int8_t*)malloc((size_t)g->n);
-      int64_t lpw[2];
       int gs = r0 <= r1 ? 0 : 1;
+      lp = (int8_t*)malloc((size_t)g->n);
       if (!lp) rc = OR_ENOMEM;
       if (rc == OR_OK) rc = or_learned_proposal(g, b, model, gs, tgt, maxw, lp, lpw);
       if (rc == OR_OK && refine_og(g, b, lp, lpw, maxw, (int)P, NULL) < 0) rc = OR_ENOMEM;
-      if (rc == OR_OK) {
-        int inf_p = pw[0] > maxw[0] || pw[1] > maxw[1];
-        int inf_l = lpw[0] > maxw[0] || lpw[1] > maxw[1];
-        int64_t cut_p = or_cut(g->n, g->xadj, g->adj, g->w, part);
-        int64_t cut_l = or_cut(g->n, g->xadj, g->adj, g->w, lp);
-        if (inf_l < inf_p || (inf_l == inf_p && cut_l < cut_p)) {
-          memcpy(part, lp, (size_t)g->n);
-          pw[0] = lpw[0];
-          pw[1] = lpw[1];
-          used_learned = 1;
-        }
+      if (rc == OR_OK && trace && trace_cap > 0) {
+        ltrace = (int64_t*)calloc((size_t)trace_cap * 8, sizeof(int64_t));
+        if (!ltrace) rc = OR_ENOMEM;
       }
-      free(lp);
-    }
-    if (rc == OR_OK && trace && L < trace_cap) {
-      int64_t* t = trace + 8 * L;
-      t[0] = g->n; t[1] = g->xadj[g->n]; t[2] = 0; t[3] = 0;
-      t[4] = or_cut(g->n, g->xadj, g->adj, g->w, part);
-      t[5] = pw[0]; t[6] = pw[1]; t[7] = pairs[L];
     }
   }
-  for (int l = L - 1; l >= 0 && rc == OR_OK; l--) {
-    OG* g = &lv[l];
-    const int64_t* b = bal ? g->vg : g->vc;
-    next = (int8_t*)malloc((size_t)(g->n > 0 ? g->n : 1));
-    if (!next) { rc = OR_ENOMEM; break; }
-    for (int32_t u = 0; u < g->n; u++) next[u] = part[cmap[l][u]];
-    free(part);
-    part = next;
-    next = NULL;
-    int64_t moves = 0;
-    int passes = refine_og(g, b, part, pw, maxw, (int)P, &moves);
-    if (passes < 0) { rc = OR_ENOMEM; break; }
-    if (trace && l < trace_cap) {
-      int64_t* t = trace + 8 * l;
-      t[0] = g->n; t[1] = g->xadj[g->n]; t[2] = passes; t[3] = moves;
-      t[4] = or_cut(g->n, g->xadj, g->adj, g->w, part);
-      t[5] = pw[0]; t[6] = pw[1]; t[7] = pairs[l];
+  if (rc == OR_OK) rc = uncoarsen(lv, cmap, L, (int)bal, pairs, maxw, (int)P, &part, pw, trace,
+                                  trace_cap);
+  if (rc == OR_OK && lp) {
+    rc = uncoarsen(lv, cmap, L, (int)bal, pairs, maxw, (int)P, &lp, lpw, ltrace, trace_cap);
+    if (rc == OR_OK) {
+      /* the plain bisection judges the learned one on the input graph: the
+         learned result is kept only when it is strictly better in
+         (infeasible, cut) after projection and refinement */
+      OG* g = &lv[0];
+      int inf_p = pw[0] > maxw[0] || pw[1] > maxw[1];
+      int inf_l = lpw[0] > maxw[0] || lpw[1] > maxw[1];
+      int64_t cut_p = or_cut(g->n, g->xadj, g->adj, g->w, part);
+      int64_t cut_l = or_cut(g->n, g->xadj, g->adj, g->w, lp);
+      if (inf_l < inf_p || (inf_l == inf_p && cut_l < cut_p)) {
+        int8_t* t = part;
+        part = lp;
+        lp = t;
+        pw[0] = lpw[0];
+        pw[1] = lpw[1];
+        used_learned = 1;
+        if (ltrace) memcpy(trace, ltrace, sizeof(int64_t) * 8 * (size_t)trace_cap);
+      }
     }
   }
+  free(lp);
+  free(ltrace);
   if (rc == OR_OK) {
     OG* g = &lv[0];
     int64_t tc = 0, tg = 0;

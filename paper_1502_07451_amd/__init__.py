@@ -96,6 +96,8 @@ def _load():
     lib.gp_batch_destroy.restype = None
     lib.gp_model_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.gp_model_create.restype = ctypes.c_int
+    lib.gp_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.gp_model_load.restype = i32
     lib.gp_model_free.argtypes = [vp]
     lib.gp_model_free.restype = None
     lib.gp_model_scores.argtypes = [vp, vp, vp]
@@ -416,6 +418,17 @@ class Model:
         if st != OK:
             raise GPError(st, "gp_model_create")
         self.handle = h
+
+    @classmethod
+    def load(cls, path: str) -> "Model":
+        """gp_model_load: the parameter blob read by the library from a file."""
+        h = ctypes.c_void_p()
+        st = _lib.gp_model_load(os.fsencode(path), ctypes.byref(h))
+        if st != OK:
+            raise GPError(st, "gp_model_load")
+        m = cls.__new__(cls)
+        m.handle = h
+        return m
 
     def close(self):
         if getattr(self, "handle", None):

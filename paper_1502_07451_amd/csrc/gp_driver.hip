@@ -105,6 +105,7 @@ struct gp_graph {
   DBuf<uint16_t> m_ha, m_hb;
   DBuf<float> m_inv, m_score;
   DBuf<int32_t> m_order;
+  DBuf<int8_t> m_lp, m_save;  // refined learned proposal (coarsest), plain level-0 result
   Ctrl* ctrl = nullptr;
   Ctrl* hctrl = nullptr;  // pinned
   // profiling
@@ -164,6 +165,7 @@ struct gp_graph {
     i_tot.release(); i_conn.release(); i_res.release(); i_ctl.release(); i_part.release();
     i_adjc.release(); i_list.release();
     m_ha.release(); m_hb.release(); m_inv.release(); m_score.release(); m_order.release();
+    m_lp.release(); m_save.release();
     if (ctrl) (void)hipFree(ctrl);
     if (hctrl) (void)hipHostFree(hctrl);
     for (int i = 0; i < prof.npool; i++)
@@ -199,9 +201,20 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
   for (int i = 0; i < g->prof.nrec; i++) {
     ProfRec& r = g->prof.recs[i];
     if (r.level != level) continue;
-    if (coarsening && (r.kind == PK_MATCH_PROPOSE || r.kind == PK_MATCH_RESOLVE))
+    if (coarsening && (r.kind == PK_MATCH_ROUND || r.kind == PK_MATCH_SETTLE))
       r.executed = (r.idx <= 1 || h.made[r.idx - 1] > 0) ? 1 : 0;
-    if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_APPLY))
+    if (coarsening) {
+      // the split of the coarse rows between the row kernels is known only
+      // now: fine entries read (adj, w, cmap of the neighbour: 16 B), coarse
+      // entries written (12 B), plus per-row bookkeeping
+      const double nf = g->lv[level]->n, mf = g->lv[level]->nnz;
+      const double nc = h.nc, mc = h.nnz_c, li = (double)h.long_in, lo = (double)h.long_out;
+      if (r.kind == PK_CONTRACT_ROWS) r.bytes = 16 * (mf - li) + 12 * (mc - lo) + 8 * nf + 20 * nc;
+      if (r.kind == PK_CONTRACT_LONG) r.bytes = 16 * li + 12 * lo;
+      if (r.kind == PK_CONTRACT_COMPACT) r.bytes = 24 * mc + 16 * nc + 4;
+    }
+    if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_SETTLE ||
+                        r.kind == PK_REFINE_APPLY))
       r.executed = r.idx < h.lvl_pass[level] ? 1 : 0;
   }
 }
@@ -524,31 +537,34 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     if (20 * (int64_t)c->n > 19 * (int64_t)f->n || L == kMaxLevels) break;
   }
   // coarsest level: greedy-growing trials
+  Level* cl = g->lv[L];
+  const bool learned = (o->flags & GP_LEARNED) && cl->n > 0 && cl->n <= kMpMaxN;
   {
-    Level* cl = g->lv[L];
     const int K = o->init_trials < cl->n ? o->init_trials : cl->n;
     if (!g->ensure_init(cl->n, K)) return GP_ENOMEM;
     const int gs = o->ratio[0] <= o->ratio[1] ? 0 : 1;
     g->prof.level = L;
     LCHK(launch_init(cl->view(bal), K, gs, P, g->ctrl, g->init_scratch(), cl->part.p, s));
-    if ((o->flags & GP_LEARNED) && cl->n > 0 && cl->n <= kMpMaxN) {
+    if (learned) {
       const size_t nh = (size_t)cl->n * kMpH;
       if (!g->m_ha.ensure(nh) || !g->m_hb.ensure(nh) || !g->m_inv.ensure(cl->n) ||
-          !g->m_score.ensure(cl->n) || !g->m_order.ensure(cl->n))
+          !g->m_score.ensure(cl->n) || !g->m_order.ensure(cl->n) || !g->m_lp.ensure(cl->n) ||
+          !g->m_save.ensure(n))
         return GP_ENOMEM;
       MpScratch ms{g->m_ha.p, g->m_hb.p, g->m_inv.p, g->m_score.p, g->m_order.p};
-      LCHK(launch_mpnn(cl->view(bal), cl->vc.p, cl->vg.p, o->model, g->i_tot.p, gs, P, g->ctrl,
-                       ms, cl->part.p, s));
+      LCHK(launch_mpnn(cl->view(bal), cl->vc.p, cl->vg.p, o->model, gs, P, g->ctrl, ms,
+                       g->m_lp.p, g->ctrl->lpw, s));
     }
   }
-  auto record = [&](int l, bool coarsest) -> gp_status {
-    if (!trace || l >= trace_cap) return GP_OK;
+  // per-level statistics of the current bisection of level l (GP_TRACE)
+  auto record = [&](int l, bool coarsest, int64_t* tr) -> gp_status {
+    if (!tr || l >= trace_cap) return GP_OK;
     Level* lvl = g->lv[l];
     LCHK(launch_final_stats(lvl->view(bal), lvl->vc.p, lvl->vg.p, lvl->part.p, g->ctrl,
                             team_width_for(lvl->n, lvl->nnz), sc.partials, s));
     gp_status e2 = read_ctrl(g);
     if (e2 != GP_OK) return e2;
-    int64_t* t = trace + 8 * l;
+    int64_t* t = tr + 8 * l;
     t[0] = lvl->n;
     t[1] = lvl->nnz;
     t[2] = coarsest ? 0 : h.ref.pass;
@@ -559,30 +575,65 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     t[7] = pairs[l];
     return GP_OK;
   };
-  if ((st = record(L, true)) != GP_OK) return st;
-  for (int l = L - 1; l >= 0; l--) {
-    Level* f = g->lv[l];
-    Level* c = g->lv[l + 1];
-    g->prof.level = l;
-    g->prof.idx = 0;
-    LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, s));
-    const int tw = team_width_for(f->n, f->nnz);
-    const LevelView fv = f->view(bal);
-    for (int p = 0; p < P; p++) {
-      g->prof.idx = p;
-      LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
-                              &g->ctrl->lvl_pass[l], s));
+  // projection and refinement from the coarsest level down to level 0, then
+  // the statistics of the level-0 bisection (read back into h)
+  auto uncoarsen = [&](int64_t* tr) -> gp_status {
+    gp_status e2 = record(L, true, tr);
+    if (e2 != GP_OK) return e2;
+    for (int l = L - 1; l >= 0; l--) {
+      Level* f = g->lv[l];
+      Level* c = g->lv[l + 1];
+      g->prof.level = l;
+      g->prof.idx = 0;
+      LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, s));
+      const int tw = team_width_for(f->n, f->nnz);
+      const LevelView fv = f->view(bal);
+      for (int p = 0; p < P; p++) {
+        g->prof.idx = p;
+        LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
+                                &g->ctrl->lvl_pass[l], s));
+      }
+      if ((e2 = record(l, false, tr)) != GP_OK) return e2;
     }
-    if ((st = record(l, false)) != GP_OK) return st;
-  }
+    Level* l0 = g->lv[0];
+    LCHK(launch_final_stats(l0->view(bal), l0->vc.p, l0->vg.p, l0->part.p, g->ctrl,
+                            team_width_for(l0->n, l0->nnz), sc.partials, s));
+    return read_ctrl(g);
+  };
+  if ((st = uncoarsen(trace)) != GP_OK) return st;
+  for (int l = L - 1; l >= 0; l--) prof_mark(g, l, false);
   Level* l0 = g->lv[0];
-  LCHK(launch_final_stats(l0->view(bal), l0->vc.p, l0->vg.p, l0->part.p, g->ctrl,
-                          team_width_for(l0->n, l0->nnz), sc.partials, s));
+  int used_learned = 0;
+  if (learned) {
+    // the plain bisection judges the learned one on the input graph: the
+    // learned proposal is carried through the same uncoarsening and kept
+    // only when it ends strictly better in (infeasible, cut)
+    const int64_t p_ext = h.res_ext, p_load[2] = {h.res_load[0], h.res_load[1]};
+    const int64_t p_time[2] = {h.res_time[0], h.res_time[1]};
+    HIPCHK(hipMemcpyAsync(g->m_save.p, l0->part.p, (size_t)n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(cl->part.p, g->m_lp.p, (size_t)cl->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(g->ctrl->ref.pw, g->ctrl->lpw, 2 * sizeof(int64_t),
+                          hipMemcpyDeviceToDevice, s));
+    std::vector<int64_t> ltr(trace ? 8 * (size_t)trace_cap : 0, 0);
+    if ((st = uncoarsen(trace ? ltr.data() : nullptr)) != GP_OK) return st;
+    const int inf_p = (p_load[0] > maxw[0] || p_load[1] > maxw[1]) ? 1 : 0;
+    const int inf_l = (h.res_load[0] > maxw[0] || h.res_load[1] > maxw[1]) ? 1 : 0;
+    if (inf_l < inf_p || (inf_l == inf_p && h.res_ext < p_ext)) {
+      used_learned = 1;
+      if (trace) memcpy(trace, ltr.data(), sizeof(int64_t) * ltr.size());
+    } else {
+      HIPCHK(hipMemcpyAsync(l0->part.p, g->m_save.p, (size_t)n, hipMemcpyDeviceToDevice, s));
+      h.res_ext = p_ext;
+      h.res_load[0] = p_load[0];
+      h.res_load[1] = p_load[1];
+      h.res_time[0] = p_time[0];
+      h.res_time[1] = p_time[1];
+    }
+  }
   const hipMemcpyKind kout =
       (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   HIPCHK(hipMemcpyAsync(part, l0->part.p, (size_t)n, kout, s));
-  if ((st = read_ctrl(g)) != GP_OK) return st;
-  for (int l = L - 1; l >= 0; l--) prof_mark(g, l, false);
+  HIPCHK(hipStreamSynchronize(s));
   r.cut = h.res_ext / 2;
   r.load[0] = h.res_load[0];
   r.load[1] = h.res_load[1];
@@ -591,7 +642,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
   r.levels = L;
   g->last_levels = L;
-  r.used_learned = h.used_learned;
+  r.used_learned = used_learned;
   r.status = GP_OK;
   *res = r;
   return GP_OK;

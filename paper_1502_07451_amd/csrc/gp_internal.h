@@ -63,12 +63,15 @@ struct Ctrl {
   // contraction
   int32_t nc, nnz_c, nlong, pad1;
   int64_t ubtot;
+  int64_t long_in, long_out;  // candidates read and entries written by the long-row kernel
   int64_t maxb_next;
   uint32_t ctr_count, ctr_long, ctr_stats, ctr_init;
   int32_t niso;           // unmatched vertices without neighbours
   uint32_t ctr_iso;
   int32_t lvl_pass[kMaxLevels + 1];  // refinement passes run on each level
   int32_t used_learned;              // the learned proposal replaced the plain one
+  int32_t pad2;
+  int64_t lpw[2];                    // part weights of the refined learned proposal
   // result of the final statistics kernel
   int64_t res_ext, res_load[2], res_time[2];
   // validation

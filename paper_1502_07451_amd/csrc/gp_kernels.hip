@@ -33,19 +33,6 @@ __global__ void k_level_reset(Ctrl* ctrl, int promote) {
 }
 
 template <int TW>
-__global__ __launch_bounds__(kBlock) void k_match_propose(LevelView lv, const int32_t* match,
-                                                          int32_t* prop, const Ctrl* ctrl,
-                                                          int round, uint64_t hs) {
-  b_match_propose<TW>(lv, match, prop, ctrl, round, hs, (int)blockIdx.x, (int)gridDim.x);
-}
-
-__global__ __launch_bounds__(kBlock) void k_match_resolve(int32_t n, int32_t* match,
-                                                          const int32_t* prop, Ctrl* ctrl,
-                                                          int round) {
-  b_match_resolve(n, match, prop, ctrl, round, (int)blockIdx.x, (int)gridDim.x);
-}
-
-template <int TW>
 __global__ __launch_bounds__(kBlock) void k_match_round(LevelView lv, int32_t* match,
                                                         const int32_t* prop_prev,
                                                         int32_t* prop_cur, Ctrl* ctrl,
@@ -278,9 +265,10 @@ __global__ void k_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_
 
 // ================================================================ profiling
 const char* const kProfNames[PK_N] = {
-    "k_match_propose", "k_match_resolve", "k_hub", "k_twohop", "k_iso", "k_contract_count",
+    "k_match_round", "k_match_settle", "k_hub", "k_twohop", "k_iso", "k_contract_count",
     "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_compact", "k_init_tot",
-    "k_init_trials", "k_refine_gain", "k_refine_apply", "k_project", "k_final_stats"};
+    "k_init_trials", "k_refine_gain", "k_refine_settle", "k_refine_apply", "k_project",
+    "k_final_stats"};
 
 thread_local Prof* g_prof = nullptr;
 
@@ -354,17 +342,6 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s) {
 }
 
 template <int TW>
-static bool propose_tw(const LevelView& lv, const int32_t* match, int32_t* prop, const Ctrl* ctrl,
-                       int round, uint64_t hs, hipStream_t s) {
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
-  const double n = lv.n, m2 = lv.nnz;
-  ProfScope ps(PK_MATCH_PROPOSE, TW, round == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
-  k_match_propose<TW><<<grid, kBlock, 0, s>>>(lv, match, prop, ctrl, round, hs);
-  KCHECK();
-  return true;
-}
-
-template <int TW>
 static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t* pb,
                       Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
@@ -372,7 +349,7 @@ static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t*
   for (int r = 0; r < R; r++) {
     int32_t* cur = (r & 1) ? pb : pa;
     const int32_t* prev = (r & 1) ? pa : pb;
-    ProfScope ps(PK_MATCH_PROPOSE, TW, r == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
+    ProfScope ps(PK_MATCH_ROUND, TW, r == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
     k_match_round<TW><<<grid, kBlock, 0, s>>>(lv, match, prev, cur, ctrl, r, hs);
   }
 }
@@ -389,28 +366,9 @@ bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, i
   }
   KCHECK();
   {
-    ProfScope ps(PK_MATCH_RESOLVE, 0, 0.0, s);
+    ProfScope ps(PK_MATCH_SETTLE, 0, 0.0, s);
     k_match_settle<<<grid_for(lv.n, kBlock * 4), kBlock, 0, s>>>(lv.n, match,
                                                                   ((R - 1) & 1) ? prop_b : prop_a);
-  }
-  KCHECK();
-  return true;
-}
-
-bool launch_match_round(const LevelView& lv, int32_t* match, int32_t* prop, Ctrl* ctrl, int round,
-                        uint64_t hs, int tw, hipStream_t s) {
-  bool ok;
-  switch (tw) {
-    case 4: ok = propose_tw<4>(lv, match, prop, ctrl, round, hs, s); break;
-    case 8: ok = propose_tw<8>(lv, match, prop, ctrl, round, hs, s); break;
-    case 16: ok = propose_tw<16>(lv, match, prop, ctrl, round, hs, s); break;
-    case 32: ok = propose_tw<32>(lv, match, prop, ctrl, round, hs, s); break;
-    default: ok = propose_tw<64>(lv, match, prop, ctrl, round, hs, s); break;
-  }
-  if (!ok) return false;
-  {
-    ProfScope ps(PK_MATCH_RESOLVE, 0, round == 0 ? 8.0 * lv.n : 0.0, s);
-    k_match_resolve<<<grid_for(lv.n, kBlock * 4), kBlock, 0, s>>>(lv.n, match, prop, ctrl, round);
   }
   KCHECK();
   return true;
@@ -491,8 +449,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   const int ntc1 = ntc > 0 ? ntc : 1;
   const int g = grid_for(ntc1, 1, 4096);
   {
-    // fine rows read once (12 B per entry) plus cmap; coarse rows written once
-    ProfScope ps(PK_CONTRACT_ROWS, 0, 12.0 * lv.nnz + 4.0 * lv.n + 4.0 * (lv.n + 1), s);
+    // algorithmic bytes are set after the level (they depend on the long rows)
+    ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
     k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
                                          sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1);
   }
@@ -551,7 +509,7 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
   if (!ok) return false;
   if (lv.n <= kSettleMax) {
     // decision, moves and pass bookkeeping in one single-block launch
-    ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
+    ProfScope ps(PK_REFINE_SETTLE, 0, 0.0, s);
     k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out);
     KCHECK();
     return true;

@@ -37,9 +37,10 @@ int team_width_for(int32_t n, int64_t nnz);
 
 // ---- per-launch profiling (HIP events), enabled by the driver for one call
 enum ProfKind {
-  PK_MATCH_PROPOSE, PK_MATCH_RESOLVE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
+  PK_MATCH_ROUND, PK_MATCH_SETTLE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
   PK_CONTRACT_MAP, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_COMPACT, PK_INIT_TOT,
-  PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_APPLY, PK_PROJECT, PK_FINAL_STATS, PK_N
+  PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_SETTLE, PK_REFINE_APPLY, PK_PROJECT,
+  PK_FINAL_STATS, PK_N
 };
 extern const char* const kProfNames[PK_N];
 
@@ -73,8 +74,6 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s);
 // prop_a / prop_b: two int32[n] proposal buffers
 bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
                          Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s);
-bool launch_match_round(const LevelView& lv, int32_t* match, int32_t* prop, Ctrl* ctrl, int round,
-                        uint64_t hs, int tw, hipStream_t s);
 bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratch& sc,
                    uint64_t hs, int tw, hipStream_t s);
 bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t* vc,

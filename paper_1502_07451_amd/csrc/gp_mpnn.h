@@ -53,8 +53,10 @@ inline int next_pow2_host(int x) {
 
 bool launch_mpnn_scores(const LevelView& lv, const int64_t* vc, const int64_t* vg,
                         const void* model, const MpScratch& ms, hipStream_t s);
+// the refined learned proposal of the coarsest graph: assignment to lp_out
+// (int8[n]), part weights to lpw_out (int64[2], device)
 bool launch_mpnn(const LevelView& lv, const int64_t* vc, const int64_t* vg, const void* model,
-                 const int64_t* tot, int gs, int npass, Ctrl* ctrl, const MpScratch& ms,
-                 int8_t* out_part, hipStream_t s);
+                 int gs, int npass, const Ctrl* ctrl, const MpScratch& ms, int8_t* lp_out,
+                 int64_t* lpw_out, hipStream_t s);
 
 }  // namespace gpk

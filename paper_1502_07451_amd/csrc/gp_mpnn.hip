@@ -2,9 +2,10 @@
 //
 // A 3-layer message-passing network (hidden size 64, BF16 weights, FP32
 // accumulation) scores the vertices of the coarsest graph; the best scores
-// fill the grown side; the LDS refinement of the initial bisection follows;
-// the result replaces the plain one only when it is strictly better in
-// (infeasible, cut).  The network orders vertices, nothing more: the
+// fill the grown side; the LDS refinement of the initial bisection follows.
+// That bisection is projected and refined down to the input graph beside the
+// plain one, and replaces it only when it ends strictly better in
+// (infeasible, cut) there.  The network orders vertices, nothing more: the
 // partition arithmetic stays integer.
 //
 // Inference uses only correctly rounded FP32 fma and multiplication in a
@@ -20,6 +21,7 @@
 //   score   = fma chain of wo[k] h3[k], k ascending, from bo
 // Parameter blob (BF16 bits): Win[64][4], b_in[64], 3 x (Ws[64][64],
 // Wn[64][64], b[64]), wo[64], bo - 25,153 values.
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
@@ -113,15 +115,16 @@ __global__ __launch_bounds__(kBlock) void k_mp_score(int32_t n, const uint16_t* 
   }
 }
 
-// Proposal, refinement and acceptance check for the coarsest graph, one block.
-// Phase 1 sorts (score key desc, id asc) in LDS and writes the order to
-// `order`; phase 2 fills the grown side, computes the gains of that
-// assignment, refines it and keeps it when strictly better than the plain
-// bisection already in out_part / ctrl->ref.
-__global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const int64_t* tot,
-                                                       const float* score, int32_t* order,
-                                                       int gs, int npass, Ctrl* ctrl,
-                                                       int8_t* out_part, int32_t* used) {
+// Proposal and refinement for the coarsest graph, one block.  Phase 1 sorts
+// (score key desc, id asc) in LDS and writes the order to `order`; phase 2
+// fills the grown side, computes the gains of that assignment and refines
+// it.  The refined bisection goes to lp_out and its part weights to
+// lpw_out; the host driver carries it through the uncoarsening beside the
+// plain one and keeps the better of the two on the input graph.
+__global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const float* score,
+                                                       int32_t* order, int gs, int npass,
+                                                       const Ctrl* ctrl, int8_t* lp_out,
+                                                       int64_t* lpw_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ SelShared sel;
   __shared__ RefCtl srf;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const int64
     for (int i = threadIdx.x; i < n; i += kBlock) order[i] = (int32_t)(~(uint32_t)key[i]);
     __syncthreads();
   }
-  // ---- phase 2: fill, gains, refinement, acceptance check
+  // ---- phase 2: fill, gains, refinement
   int64_t* s_gain = (int64_t*)lds;
   int64_t* s_b = s_gain + n;
   int8_t* s_part = (int8_t*)(s_b + n);
@@ -219,38 +222,24 @@ __global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const int64
   }
   __syncthreads();
   lds_refine<kBlock>(lv, s_gain, s_b, s_part, s_mv, srf, sel);
-  int64_t q = 0;
-  for (int32_t v = threadIdx.x; v < n; v += kBlock) q += s_gain[v] + tot[v];
-  q = block_sum<kBlock, int64_t>(q, sml);
-  const int64_t cut_l = q / 4;
-  const int inf_l = (srf.pw[0] > srf.maxw[0] || srf.pw[1] > srf.maxw[1]) ? 1 : 0;
-  const int inf_p = (ctrl->ref.pw[0] > ctrl->ref.maxw[0] || ctrl->ref.pw[1] > ctrl->ref.maxw[1]);
-  const int64_t cut_p = ctrl->ref.last_cut;
-  const bool better = inf_l < inf_p || (inf_l == inf_p && cut_l < cut_p);
-  __syncthreads();
-  if (better) {
-    for (int32_t v = threadIdx.x; v < n; v += kBlock) out_part[v] = s_part[v];
-    if (threadIdx.x == 0) {
-      ctrl->ref.pw[0] = srf.pw[0];
-      ctrl->ref.pw[1] = srf.pw[1];
-      ctrl->ref.last_cut = cut_l;
-    }
+  for (int32_t v = threadIdx.x; v < n; v += kBlock) lp_out[v] = s_part[v];
+  if (threadIdx.x == 0) {
+    lpw_out[0] = srf.pw[0];
+    lpw_out[1] = srf.pw[1];
   }
-  if (threadIdx.x == 0) *used = better ? 1 : 0;
 }
 
 bool launch_mpnn_scores(const LevelView& lv, const int64_t* vc, const int64_t* vg,
                         const void* model, const MpScratch& ms, hipStream_t s);
 
 bool launch_mpnn(const LevelView& lv, const int64_t* vc, const int64_t* vg, const void* model,
-                 const int64_t* tot, int gs, int npass, Ctrl* ctrl, const MpScratch& ms,
-                 int8_t* out_part, hipStream_t s) {
+                 int gs, int npass, const Ctrl* ctrl, const MpScratch& ms, int8_t* lp_out,
+                 int64_t* lpw_out, hipStream_t s) {
   if (!launch_mpnn_scores(lv, vc, vg, model, ms, s)) return false;
   const size_t dyn = (size_t)lv.n * 19 + 16 > (size_t)next_pow2_host(lv.n) * 8
                          ? (size_t)lv.n * 19 + 16
                          : (size_t)next_pow2_host(lv.n) * 8;
-  k_mp_propose<<<1, kBlock, dyn, s>>>(lv, tot, ms.score, ms.order, gs, npass, ctrl, out_part,
-                                      &ctrl->used_learned);
+  k_mp_propose<<<1, kBlock, dyn, s>>>(lv, ms.score, ms.order, gs, npass, ctrl, lp_out, lpw_out);
   return hipGetLastError() == hipSuccess;
 }
 
@@ -299,6 +288,26 @@ gp_status gp_model_create(const uint16_t* params, int32_t count, const void** mo
   m->magic = kMpMagic;
   *model = m;
   return GP_OK;
+}
+
+gp_status gp_model_load(const char* path, const void** model) {
+  if (!model || !path) return GP_EINVAL;
+  *model = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return GP_EINVAL;
+  // the file is the raw blob: kMpNParam little-endian BF16 values, nothing else
+  uint16_t* buf = new (std::nothrow) uint16_t[kMpNParam + 1];
+  if (!buf) {
+    fclose(f);
+    return GP_ENOMEM;
+  }
+  const size_t got = fread(buf, sizeof(uint16_t), kMpNParam + 1, f);
+  const bool err = ferror(f) != 0;
+  fclose(f);
+  gp_status st = (err || got != (size_t)kMpNParam) ? GP_EMODEL
+                                                   : gp_model_create(buf, kMpNParam, model);
+  delete[] buf;
+  return st;
 }
 
 void gp_model_free(const void* model) {

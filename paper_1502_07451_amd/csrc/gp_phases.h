@@ -28,6 +28,8 @@ __device__ __forceinline__ void b_level_reset(Ctrl* ctrl, int promote, int bid_,
     ctrl->nnz_c = 0;
     ctrl->nlong = 0;
     ctrl->ubtot = 0;
+    ctrl->long_in = 0;
+    ctrl->long_out = 0;
     ctrl->maxb_next = 0;
   }
 }
@@ -646,6 +648,7 @@ __device__ __forceinline__ void b_contract_rows(
         const int slot = atomicAdd(&wctrl->nlong, 1);
         longlist[slot] = c;
         cnt[c] = 0;
+        atomicAdd((unsigned long long*)&wctrl->long_in, (unsigned long long)L);
       }
     }
     __syncthreads();
@@ -737,6 +740,7 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
     if (threadIdx.x == 0) {
       cnt[c] = k;
       atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
+      atomicAdd((unsigned long long*)&ctrl->long_out, (unsigned long long)k);
     }
   }
   if (!inline_tail) return;

@@ -44,3 +44,20 @@ def test_host_only_entry_points():
     assert lib.gp_ratio_from_times(0, 0, out) == 1
     lib.gp_strerror.restype = ctypes.c_char_p
     assert b"self loop" in lib.gp_strerror(4)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgp.so not built")
+def test_model_load_rejects_bad_files(tmp_path):
+    # both checks happen before the library touches the device
+    lib = ctypes.CDLL(LIB)
+    lib.gp_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p(1)
+    assert lib.gp_model_load(os.fsencode(str(tmp_path / "missing.bin")), ctypes.byref(h)) == 1
+    assert not h.value
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"\0" * (2 * 25153 - 2))
+    assert lib.gp_model_load(os.fsencode(str(short)), ctypes.byref(h)) == 9
+    long_ = tmp_path / "long.bin"
+    long_.write_bytes(b"\0" * (2 * 25153 + 2))
+    assert lib.gp_model_load(os.fsencode(str(long_)), ctypes.byref(h)) == 9
+    assert not h.value

@@ -132,19 +132,30 @@ def test_batch_uneven_sizes(gp):
     check_against_oracle(b, graphs, got, res, kw)
 
 
-def test_batch_full_4096_sampled(gp):
+def test_batch_full_4096(gp):
     """The 4,096-graph batch at full size (sizes 100..50,000, half Cholesky,
-    half layered), as the benchmark runs it; 40 sampled graphs against the
-    oracle and every graph against the single-graph GPU path's totals."""
+    half layered), as the benchmark runs it: every graph's assignment, cut,
+    loads, times, feasibility and level count against the oracle (run over
+    the graphs on a host thread pool), and the largest graphs also through
+    the single-graph GPU path."""
+    import concurrent.futures
+    import os
     graphs = dagen.batch(4096, 100, 50000, 0)
     kw = dict(ratio=(1, 4), eps_ppm=30000)
     say("case batch full 4096")
     b, got, res = run_batch(gp, graphs, kw)
     assert all(r.status == 0 for r in res)
-    rng = np.random.default_rng(0)
-    sample = sorted(set(rng.integers(0, 4096, 36).tolist()) | {0, 1, 4094, 4095})
-    check_against_oracle(b, graphs, got, res, kw, which=sample)
-    # the largest graphs through the single-graph path as well
+    oo = oracle.Options(**kw)
+    with concurrent.futures.ThreadPoolExecutor(min(os.cpu_count() or 1, 16)) as ex:
+        refs = list(ex.map(lambda g: oracle.partition(g, oo), graphs))
+    bad = []
+    for i, (ref, r) in enumerate(zip(refs, res)):
+        p = got[b.voff[i]:b.voff[i + 1]]
+        if not (ref.status == 0 and np.array_equal(p, ref.part) and r.cut == ref.cut and
+                (r.load[0], r.load[1]) == ref.load and (r.time[0], r.time[1]) == ref.time and
+                r.feasible == ref.feasible and r.levels == ref.levels):
+            bad.append(i)
+    assert not bad, f"{len(bad)} graphs differ from the oracle, first {bad[:8]}"
     sizes = np.diff(b.voff)
     for g in np.argsort(-sizes)[:6].tolist():
         h = gp.create(graphs[g])

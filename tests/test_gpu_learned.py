@@ -93,3 +93,48 @@ def test_trained_weights_match_oracle(gp):
     model.close()
     assert ref.status == 0 and res.used_learned == ref.used_learned
     assert np.array_equal(part.cpu().numpy(), ref.part) and res.cut == ref.cut
+
+
+def test_trained_weights_layered1m(gp):
+    """The learned path with the committed trained weights on the 1,000,000-
+    vertex layered DAG (1:3, eps 5 %), its other evaluation graph: the same
+    assignment, cut, loads and acceptance decision as the oracle."""
+    import os
+    from paper_1502_07451_amd import learn
+    if not os.path.exists(learn.WEIGHTS_PATH):
+        pytest.skip("no trained weights")
+    g = dagen.config_layered1m()
+    say("case trained weights layered1m")
+    model = gp.Model.load(learn.WEIGHTS_PATH)
+    h = gp.create(g)
+    part, res = h.partition(gp.options(ratio=(1, 3), eps_ppm=50000, flags=gp.LEARNED,
+                                       model=model.handle))
+    got = part.cpu().numpy()
+    h.close()
+    model.close()
+    ref = oracle.partition(g, oracle.Options(ratio=(1, 3), eps_ppm=50000,
+                                             flags=oracle.FLAG_LEARNED),
+                           model=learn.load_weights())
+    assert ref.status == 0 and res.used_learned == ref.used_learned
+    assert np.array_equal(got, ref.part) and res.cut == ref.cut
+    assert (res.load[0], res.load[1]) == ref.load and res.levels == ref.levels
+
+
+def test_model_load_equals_create(gp):
+    """gp_model_load reads the blob file the training driver writes; its scores
+    equal those of gp_model_create on the same parameters."""
+    import os
+    from paper_1502_07451_amd import learn
+    if not os.path.exists(learn.WEIGHTS_PATH):
+        pytest.skip("no trained weights")
+    g = dagen.cholesky(12, 512, jitter_pm=100, seed=3)
+    say("case model load")
+    a = gp.Model.load(learn.WEIGHTS_PATH)
+    b = gp.Model(learn.load_weights())
+    h = gp.create(g)
+    sa = h.scores(a).cpu().numpy()
+    sb = h.scores(b).cpu().numpy()
+    h.close()
+    a.close()
+    b.close()
+    assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))

@@ -272,3 +272,60 @@ def test_learned_proposal_kept_in_the_pipeline():
     r = oracle.partition(g, oracle.Options(**opts, flags=oracle.FLAG_LEARNED), model=model)
     assert r.status == 0 and r.used_learned == 1 and r.cut == 2 and r.feasible
     assert r.part.tolist() == [1, 1, 1, 1, 1, 0, 0, 0, 0]
+
+
+# ------------------------------------------------- judge on the input graph
+
+def _key(r):
+    return (1 - int(r.feasible), int(r.cut))
+
+
+def _judge_invariants(g, kw, model):
+    plain = oracle.partition(g, oracle.Options(**kw))
+    lr = oracle.partition(g, oracle.Options(**kw, flags=oracle.FLAG_LEARNED), model=model)
+    assert plain.status == 0 and lr.status == 0
+    assert lr.levels == plain.levels
+    if lr.used_learned:
+        # kept only when strictly better on the input graph
+        assert _key(lr) < _key(plain)
+    else:
+        assert np.array_equal(lr.part, plain.part) and lr.cut == plain.cut
+        assert lr.load == plain.load and lr.time == plain.time
+    return plain, lr
+
+
+def test_learned_never_worse_than_plain_random():
+    """The plain bisection judges the learned one after both are projected and
+    refined to the input graph: the learned form never ends worse than the
+    plain one, and it equals the plain result whenever it is not kept.  A
+    judge at the coarsest level breaks this on some of these graphs."""
+    rng = np.random.default_rng(77)
+    kept = 0
+    for i in range(24):
+        g = dagen.layered(int(rng.integers(600, 5000)), int(rng.integers(3, 16)), rate=3,
+                          seed=int(rng.integers(0, 10**6)))
+        P = (rng.standard_normal(oracle.mpnn_nparam()) * 0.3).astype(np.float32)
+        bits = (P.view(np.uint32) >> 16).astype(np.uint16)   # truncation to BF16 is fine here
+        kw = dict(ratio=(1, int(rng.integers(1, 5))), eps_ppm=30000,
+                  coarsen_to=int(rng.choice([32, 128, 512])))
+        _, lr = _judge_invariants(g, kw, bits)
+        kept += lr.used_learned
+    assert 0 < kept < 24
+
+
+def test_learned_judged_after_uncoarsening_cholesky64():
+    """The committed trained weights on the tiled Cholesky T=64 DAG (1:4, 3 %):
+    the learned proposal beats the best greedy trial on the coarsest graph,
+    but after projection and refinement it ends with a larger cut, so the
+    judge on the input graph keeps the plain result.  On the tiled LU T=48
+    DAG the learned run ends with a smaller cut and is kept."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1502_07451_amd", "mpnn_weights.bin")
+    model = np.fromfile(path, dtype=np.uint16)
+    chol, lu = dagen.config_cholesky64_lu48()
+    kw = dict(ratio=(1, 4), eps_ppm=30000)
+    plain, lr = _judge_invariants(chol, kw, model)
+    assert lr.used_learned == 0 and lr.cut == plain.cut
+    plain, lr = _judge_invariants(lu, kw, model)
+    assert lr.used_learned == 1 and lr.cut < plain.cut
