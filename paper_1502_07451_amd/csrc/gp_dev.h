@@ -719,6 +719,128 @@ __device__ int wave_sort_emit(int L, const Loader& ld, int32_t* sk, int64_t* sv,
   return total;
 }
 
+// ------------------------------------------------- key-only wave sorts
+// Bitonic network on one int32 key per lane, 64 lanes, ascending; N
+// independent columns at once (one key each per lane) so that the lane
+// exchanges of one column overlap the compares of the others.
+template <int N, int SIZE, int STRIDE>
+__device__ __forceinline__ void kbitonic_step(int32_t (&k)[N]) {
+  const int lane = lane_id();
+  const bool up = (lane & SIZE) == 0;
+  const bool lower = (lane & STRIDE) == 0;
+  int32_t k2[N];
+#pragma unroll
+  for (int c = 0; c < N; c++) k2[c] = xor_lane<STRIDE>(k[c]);
+#pragma unroll
+  for (int c = 0; c < N; c++)
+    k[c] = (lower == up) ? (k2[c] < k[c] ? k2[c] : k[c]) : (k2[c] > k[c] ? k2[c] : k[c]);
+  if constexpr (STRIDE > 1) kbitonic_step<N, SIZE, STRIDE / 2>(k);
+}
+
+template <int N, int SIZE>
+__device__ __forceinline__ void kbitonic_stage(int32_t (&k)[N]) {
+  kbitonic_step<N, SIZE, SIZE / 2>(k);
+  if constexpr (SIZE < 64) kbitonic_stage<N, SIZE * 2>(k);
+}
+
+// half-cleaners with strides 32, 16, ..., 1, all ascending: sorts bitonic
+// 64-lane sequences whose halves are already split (lower <= upper)
+template <int N, int STRIDE>
+__device__ __forceinline__ void khalf_clean(int32_t (&k)[N]) {
+  const bool lower = (lane_id() & STRIDE) == 0;
+  int32_t k2[N];
+#pragma unroll
+  for (int c = 0; c < N; c++) k2[c] = xor_lane<STRIDE>(k[c]);
+#pragma unroll
+  for (int c = 0; c < N; c++)
+    k[c] = lower ? (k2[c] < k[c] ? k2[c] : k[c]) : (k2[c] > k[c] ? k2[c] : k[c]);
+  if constexpr (STRIDE > 1) khalf_clean<N, STRIDE / 2>(k);
+}
+
+// one compare-exchange step over the wave's LDS keys: pair t joins slots
+// lo(t) and hi(t); U pairs per lane per iteration, all loads first (the
+// pairs of one step are disjoint)
+template <int U, class Pair>
+__device__ __forceinline__ void kstep_lds(int32_t* sk, int npairs, const Pair& pair) {
+  const int lane = lane_id();
+  for (int t0 = 0; t0 < npairs; t0 += 64 * U) {
+    int lo[U], hi[U];
+    int32_t a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) pair(t0 + u * 64 + lane, lo[u], hi[u]);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      a[u] = sk[lo[u]];
+      b[u] = sk[hi[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      sk[lo[u]] = a[u] < b[u] ? a[u] : b[u];
+      sk[hi[u]] = a[u] < b[u] ? b[u] : a[u];
+    }
+  }
+}
+
+template <class Pair>
+__device__ __forceinline__ void kstep(int32_t* sk, int npairs, const Pair& pair) {
+  if (npairs >= 256) kstep_lds<4>(sk, npairs, pair);
+  else if (npairs >= 128) kstep_lds<2>(sk, npairs, pair);
+  else kstep_lds<1>(sk, npairs, pair);
+}
+
+// the 64-key columns [r, r + N) of the wave's LDS keys through f, in registers
+template <int N, class F>
+__device__ __forceinline__ void kcolumns(int32_t* sk, int r, const F& f) {
+  const int lane = lane_id();
+  int32_t k[N];
+#pragma unroll
+  for (int c = 0; c < N; c++) k[c] = sk[(r + c) * 64 + lane];
+  f(k);
+#pragma unroll
+  for (int c = 0; c < N; c++) sk[(r + c) * 64 + lane] = k[c];
+}
+
+// Ascending sort of P2 distinct int32 keys (INT_MAX padding allowed), P2 a
+// power of two in [128, 64 * 64], in LDS private to one wave.  Columns of 64
+// consecutive keys are sorted in registers, up to four at a time; each merge
+// of two sorted blocks of `size` / 2 keys compares key j with its mirror
+// j ^ (size - 1), which leaves both halves bitonic and split, then runs
+// half-cleaners from stride size / 4 down: strides of 64 and more in LDS,
+// the last six in registers.  Every step is a fixed compare-exchange
+// network, so the result does not depend on timing.
+__device__ __forceinline__ void wave_sort_keys(int32_t* sk, int P2) {
+  const int cols = P2 >> 6;  // 2, or a multiple of 4
+  auto sort_cols = [&](auto& k) { kbitonic_stage<sizeof(k) / sizeof(k[0]), 2>(k); };
+  auto clean_cols = [&](auto& k) { khalf_clean<sizeof(k) / sizeof(k[0]), 32>(k); };
+  if (cols >= 4) {
+    for (int r = 0; r < cols; r += 4) kcolumns<4>(sk, r, sort_cols);
+  } else {
+    kcolumns<2>(sk, 0, sort_cols);
+  }
+  wave_sync();
+  for (int size = 128; size <= P2; size <<= 1) {
+    const int half = size >> 1;
+    kstep(sk, P2 >> 1, [&](int t, int& lo, int& hi) {
+      lo = (t & ~(half - 1)) * 2 + (t & (half - 1));
+      hi = lo ^ (size - 1);
+    });
+    wave_sync();
+    for (int stride = half >> 1; stride >= 64; stride >>= 1) {
+      kstep(sk, P2 >> 1, [&](int t, int& lo, int& hi) {
+        lo = (t & ~(stride - 1)) * 2 + (t & (stride - 1));
+        hi = lo + stride;
+      });
+      wave_sync();
+    }
+    if (cols >= 4) {
+      for (int r = 0; r < cols; r += 4) kcolumns<4>(sk, r, clean_cols);
+    } else {
+      kcolumns<2>(sk, 0, clean_cols);
+    }
+    wave_sync();
+  }
+}
+
 // any L: dense accumulation over windows of kWin ids (LDS acc/cnt/pres)
 template <int BS, bool MERGE, class Loader>
 __device__ int block_dense_emit(int L, const Loader& ld, int64_t* acc, int32_t* cnt,

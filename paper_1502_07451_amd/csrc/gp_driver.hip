@@ -209,8 +209,11 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
       // entries written (12 B), plus per-row bookkeeping
       const double nf = g->lv[level]->n, mf = g->lv[level]->nnz;
       const double nc = h.nc, mc = h.nnz_c, li = (double)h.long_in, lo = (double)h.long_out;
-      if (r.kind == PK_CONTRACT_ROWS) r.bytes = 16 * (mf - li) + 12 * (mc - lo) + 8 * nf + 20 * nc;
+      const double hi = (double)h.huge_in, ho = (double)h.huge_out;
+      if (r.kind == PK_CONTRACT_ROWS)
+        r.bytes = 16 * (mf - li - hi) + 12 * (mc - lo - ho) + 8 * nf + 20 * nc;
       if (r.kind == PK_CONTRACT_LONG) r.bytes = 16 * li + 12 * lo;
+      if (r.kind == PK_CONTRACT_HUGE) r.bytes = 16 * hi + 12 * ho;
       if (r.kind == PK_CONTRACT_COMPACT) r.bytes = 24 * mc + 16 * nc + 4;
     }
     if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_SETTLE ||

@@ -18,6 +18,9 @@ constexpr int kWaveCap = 512;     // longest candidate row sorted in LDS by one 
 constexpr int kRowBlockCap = 2048;  // longest candidate row sorted in LDS by one block (contraction)
 constexpr int kSortCap = 4096;    // longest candidate row sorted in LDS by one block
 constexpr int kWin = 4096;        // id window of the dense long-row merge
+constexpr int kLongCap = 4096;    // longest candidate row sorted by one wave (packed keys)
+constexpr int kPackIdBits = 12;   // position bits of a packed key: kLongCap = 2^12
+constexpr int32_t kPackMaxNc = (1 << 19) - 1;  // coarse ids below this fit a packed key
 constexpr int kMaxLevels = 48;
 constexpr int kMaxRounds = 64;
 constexpr int kInitBlock = 64;    // one wave per greedy-growing trial
@@ -61,9 +64,10 @@ struct Ctrl {
   int64_t maxb;           // largest balance weight on the current level
   int32_t made[kMaxRounds];
   // contraction
-  int32_t nc, nnz_c, nlong, pad1;
+  int32_t nc, nnz_c, nlong, nhuge;  // nhuge: rows sorted by one block each
   int64_t ubtot;
   int64_t long_in, long_out;  // candidates read and entries written by the long-row kernel
+  int64_t huge_in, huge_out;  // the same for the rows of one block each
   int64_t maxb_next;
   uint32_t ctr_count, ctr_long, ctr_stats, ctr_init;
   int32_t niso;           // unmatched vertices without neighbours

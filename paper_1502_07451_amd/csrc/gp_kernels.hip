@@ -5,7 +5,8 @@
 //               k_match_settle, k_hub, k_twohop, k_iso_count / k_iso_list /
 //               k_iso_pair
 //   contraction k_contract_count -> k_contract_map -> k_contract_rows
-//               -> k_contract_long -> k_contract_compact
+//               -> k_contract_long (one wave per row) -> k_contract_huge
+//               (one block per row) -> k_contract_compact
 // at the coarsest level
 //   initial bisection k_init_tot -> k_init_trials_lds (one trial per block)
 // per level on the way back up
@@ -108,23 +109,37 @@ __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int
 __global__ __launch_bounds__(kBlock) void k_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
     const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
-    int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c) {
+    int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, int32_t* hugelist) {
   __shared__ __align__(16) unsigned char lds[kRowBlockCap * 12];
   b_contract_rows(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist, wctrl,
-                  ntiles_c, lds, (int)blockIdx.x, (int)gridDim.x);
+                  ntiles_c, lds, (int)blockIdx.x, (int)gridDim.x, hugelist);
 }
 
-__global__ __launch_bounds__(kBlock) void k_contract_long(LevelView lv, const int32_t* cmap,
+// one wave per long row (packed-key sort in the wave's 16 KB of LDS)
+__global__ __launch_bounds__(64) void k_contract_long(LevelView lv, const int32_t* cmap,
+                                                      const int32_t* cmem0, const int32_t* cmem1,
+                                                      const int64_t* toff, Ctrl* ctrl,
+                                                      int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
+                                                      int64_t* tile_cnt,
+                                                      const int32_t* longlist) {
+  __shared__ int32_t sk[kLongCap];
+  b_contract_longw(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist, sk,
+                   (int)blockIdx.x, (int)gridDim.x);
+}
+
+// one block per row of more than kLongCap candidates (or on a level whose
+// coarse ids do not fit a packed key)
+__global__ __launch_bounds__(kBlock) void k_contract_huge(LevelView lv, const int32_t* cmap,
                                                           const int32_t* cmem0,
                                                           const int32_t* cmem1,
                                                           const int64_t* toff, Ctrl* ctrl,
                                                           int32_t* tmpk, int64_t* tmpv,
                                                           int32_t* cnt, int64_t* tile_cnt,
-                                                          const int32_t* longlist,
+                                                          const int32_t* hugelist,
                                                           int ntiles_c) {
   extern __shared__ __align__(16) unsigned char dyn_long[];
-  b_contract_long(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist,
-                  ntiles_c, dyn_long, true, (int)blockIdx.x, (int)gridDim.x, false);
+  b_contract_long(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, hugelist,
+                  ntiles_c, dyn_long, true, (int)blockIdx.x, (int)gridDim.x, false, true);
 }
 
 __global__ __launch_bounds__(kBlock) void k_tile_scan(Ctrl* ctrl, int64_t* tile_cnt, int ntiles_c) {
@@ -266,7 +281,8 @@ __global__ void k_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_
 // ================================================================ profiling
 const char* const kProfNames[PK_N] = {
     "k_match_round", "k_match_settle", "k_hub", "k_twohop", "k_iso", "k_contract_count",
-    "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_compact", "k_init_tot",
+    "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_huge",
+    "k_contract_compact", "k_init_tot",
     "k_init_trials", "k_refine_gain", "k_refine_settle", "k_refine_apply", "k_project",
     "k_final_stats"};
 
@@ -451,23 +467,34 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   {
     // algorithmic bytes are set after the level (they depend on the long rows)
     ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
-    k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
-                                         sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1);
+    k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(
+        lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt, sc.tile_cnt,
+        sc.longlist, ctrl, ntc1, sc.prop);
+  }
+  KCHECK();
+  {
+    ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
+    // rows of kWaveCap..kLongCap candidates, one wave each; ten waves fit a
+    // compute unit's LDS
+    const int gw = grid_for(nc_max, 64, 2560) < 256 ? 256 : grid_for(nc_max, 64, 2560);
+    k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
+                                      sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist);
   }
   KCHECK();
   // the dense window plus a staged copy of one row (96 KB)
   const size_t dyn = (size_t)(kWin + kSortCap) * (sizeof(int64_t) + sizeof(int32_t));
-  static const bool long_attr =
-      hipFuncSetAttribute((const void*)k_contract_long, hipFuncAttributeMaxDynamicSharedMemorySize,
+  static const bool huge_attr =
+      hipFuncSetAttribute((const void*)k_contract_huge, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)dyn) == hipSuccess;
-  if (!long_attr) return false;
+  if (!huge_attr) return false;
   {
-    ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
-    // rows of more than kWaveCap candidates: one block each (a level of a large
-    // graph can have thousands of them)
+    ProfScope ps(PK_CONTRACT_HUGE, 0, 0.0, s);
+    // the rest of the long rows (sc.prop is free during contraction: it holds
+    // their list), one block each
     const int glong = grid_for(nc_max, 512, 1024) < 64 ? 64 : grid_for(nc_max, 512, 1024);
-    k_contract_long<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
-                                            sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist, ntc1);
+    k_contract_huge<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl,
+                                               sc.tmpk, sc.tmpv, sc.cnt, sc.tile_cnt, sc.prop,
+                                               ntc1);
   }
   KCHECK();
   k_tile_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_cnt, ntc1);

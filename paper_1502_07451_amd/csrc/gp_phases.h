@@ -30,6 +30,9 @@ __device__ __forceinline__ void b_level_reset(Ctrl* ctrl, int promote, int bid_,
     ctrl->ubtot = 0;
     ctrl->long_in = 0;
     ctrl->long_out = 0;
+    ctrl->nhuge = 0;
+    ctrl->huge_in = 0;
+    ctrl->huge_out = 0;
     ctrl->maxb_next = 0;
   }
 }
@@ -570,45 +573,78 @@ __device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32
   if (lane == 0) *cnt_out = cnt;
 }
 
-// Rows are sorted in small groups per block: one 16-lane team per short row
-// (<= 16 candidates), and for longer rows one wave per row (in registers up
-// to 64, in the wave's private LDS up to kWaveCap); rows beyond that go to
-// the long list.  Many small groups keep enough rows in flight to hide the
-// gather latency at the coarse levels, where rows are long and few.
-constexpr int kRowsPerBlock = 4;
+__device__ __forceinline__ int wave_row_packed(const LevelView& lv, const int32_t* cmap,
+                                               const CoarseRowLoader& ld, int32_t c, int L,
+                                               int32_t* sk, int32_t* ok, int64_t* ov);
+
+// Rows are sorted in groups of kRowsPerBlock per block, each by a team sized
+// to its candidate count: a 16-lane team for <= 16 candidates (team i takes
+// row i), a 32-lane team for <= 32, a wave for <= 64 (all three in
+// registers), a wave in its private LDS for <= kWaveCap; longer rows go to
+// the lists of the long-row kernels.  Sixteen rows per block keep enough
+// rows in flight to hide the gather latency on the large sparse levels.
+constexpr int kRowsPerBlock = 16;
 
 __device__ __forceinline__ void b_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
     const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
     int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, unsigned char* lds,
-    int bid_, int nblk_) {
+    int bid_, int nblk_, int32_t* hugelist = nullptr) {
   // lds: kBlock/64 wave-private regions of kWaveCap x (int64 + int32) bytes
   int64_t* sv = (int64_t*)lds;
   int32_t* sk = (int32_t*)(sv + kRowBlockCap);
-  __shared__ int32_t s_e0[kRowsPerBlock], s_d0[kRowsPerBlock], s_e1[kRowsPerBlock],
-      s_len[kRowsPerBlock];
+  constexpr int R = kRowsPerBlock;
+  __shared__ int32_t s_e0[R], s_d0[R], s_e1[R], s_len[R];
+  // rows of each register or LDS class: [0] <= 32, [1] <= 64, [2] <= kWaveCap
+  __shared__ int8_t s_list[3][R];
+  __shared__ int32_t s_count[3];
   static_assert(kWaveCap * (kBlock / 64) <= kRowBlockCap, "wave regions exceed the block region");
-  static_assert(kRowsPerBlock <= kBlock / 16 && kRowsPerBlock % (kBlock / 64) == 0,
-                "a 16-lane team per row and whole rows per wave");
-  constexpr int kRowsPerWave = kRowsPerBlock / (kBlock / 64);
-  static_assert(kTileC % kRowsPerBlock == 0, "row groups nest in compaction tiles");
+  static_assert(R == kBlock / 16 && R <= 64, "a 16-lane team per row; the rows fit one wave");
+  static_assert(kTileC % R == 0, "row groups nest in compaction tiles");
   (void)ntiles_c;
   const int32_t nc = ctrl->nc;
   const int wave = threadIdx.x / 64;
-  const int32_t ngroups = (nc + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int32_t ngroups = (nc + R - 1) / R;
   for (int32_t grp = bid_; grp < ngroups; grp += nblk_) {
-    const int32_t c0 = grp * kRowsPerBlock;
-    const int rows = c0 + kRowsPerBlock < nc ? kRowsPerBlock : nc - c0;
-    if ((int)threadIdx.x < rows) {
-      const int32_t c = c0 + (int32_t)threadIdx.x;
-      const int32_t m0 = cmem0[c], m1 = cmem1[c];
-      const int32_t e0 = lv.xadj[m0], d0 = lv.xadj[m0 + 1] - e0;
-      const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0;
-      const int32_t d1 = m1 >= 0 ? lv.xadj[m1 + 1] - e1 : 0;
-      s_e0[threadIdx.x] = e0;
-      s_d0[threadIdx.x] = d0;
-      s_e1[threadIdx.x] = e1;
-      s_len[threadIdx.x] = d0 + d1;
+    const int32_t c0 = grp * R;
+    const int rows = c0 + R < nc ? R : nc - c0;
+    if (threadIdx.x < 64) {
+      // wave 0 reads the rows' members and sorts the rows into classes
+      int L = 0;
+      if ((int)threadIdx.x < rows) {
+        const int32_t c = c0 + (int32_t)threadIdx.x;
+        const int32_t m0 = cmem0[c], m1 = cmem1[c];
+        const int32_t e0 = lv.xadj[m0], d0 = lv.xadj[m0 + 1] - e0;
+        const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0;
+        const int32_t d1 = m1 >= 0 ? lv.xadj[m1 + 1] - e1 : 0;
+        L = d0 + d1;
+        s_e0[threadIdx.x] = e0;
+        s_d0[threadIdx.x] = d0;
+        s_e1[threadIdx.x] = e1;
+        s_len[threadIdx.x] = L;
+        if (L > kWaveCap) {
+          // one wave per row when the packed keys fit, else one block per row
+          if (!hugelist || (L <= kLongCap && nc < kPackMaxNc)) {
+            const int slot = atomicAdd(&wctrl->nlong, 1);
+            longlist[slot] = c;
+            atomicAdd((unsigned long long*)&wctrl->long_in, (unsigned long long)L);
+          } else {
+            const int slot = atomicAdd(&wctrl->nhuge, 1);
+            hugelist[slot] = c;
+            atomicAdd((unsigned long long*)&wctrl->huge_in, (unsigned long long)L);
+          }
+          cnt[c] = 0;
+        }
+      }
+      const bool in_rows = (int)threadIdx.x < rows;
+      const bool cls[3] = {in_rows && L > 16 && L <= 32, in_rows && L > 32 && L <= 64,
+                           in_rows && L > 64 && L <= kWaveCap};
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const uint64_t m = __ballot(cls[q]);
+        if (cls[q]) s_list[q][__popcll(m & lanemask_lt())] = (int8_t)threadIdx.x;
+        if (threadIdx.x == 0) s_count[q] = __popcll(m);
+      }
     }
     __syncthreads();
     auto loader = [&](int i) {
@@ -630,26 +666,30 @@ __device__ __forceinline__ void b_contract_rows(
         team_row<16>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
       }
     }
-    for (int q = 0; q < kRowsPerWave; q++) {
-      const int i = kRowsPerWave * wave + q;
-      if (i >= rows) break;
-      const int L = s_len[i];
-      if (L <= 16) continue;
+    for (int q = (int)threadIdx.x / 32; q < s_count[0]; q += kBlock / 32) {
+      const int i = s_list[0][q];
       const int32_t c = c0 + i;
-      if (L <= 64) {
-        team_row<64>(loader(i), L, tmpk + toff[c], tmpv + toff[c], &cnt[c]);
-      } else if (L <= kWaveCap) {
+      team_row<32>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+    }
+    for (int q = wave; q < s_count[1]; q += kBlock / 64) {
+      const int i = s_list[1][q];
+      const int32_t c = c0 + i;
+      team_row<64>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
+    }
+    for (int q = wave; q < s_count[2]; q += kBlock / 64) {
+      const int i = s_list[2][q];
+      const int32_t c = c0 + i;
+      int k;
+      if (nc < kPackMaxNc) {
+        // packed keys in the wave's region (kWaveCap keys)
+        k = wave_row_packed(lv, cmap, loader(i), c, s_len[i], sk + wave * kWaveCap,
+                            tmpk + toff[c], tmpv + toff[c]);
+      } else {
         bool dummy = false;
-        const int k = wave_sort_emit<true>(L, loader(i), sk + wave * kWaveCap,
-                                           sv + wave * kWaveCap, tmpk + toff[c], tmpv + toff[c],
-                                           &dummy);
-        if (lane_id() == 0) cnt[c] = k;
-      } else if (lane_id() == 0) {
-        const int slot = atomicAdd(&wctrl->nlong, 1);
-        longlist[slot] = c;
-        cnt[c] = 0;
-        atomicAdd((unsigned long long*)&wctrl->long_in, (unsigned long long)L);
+        k = wave_sort_emit<true>(s_len[i], loader(i), sk + wave * kWaveCap, sv + wave * kWaveCap,
+                                 tmpk + toff[c], tmpv + toff[c], &dummy);
       }
+      if (lane_id() == 0) cnt[c] = k;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -686,7 +726,8 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
                                                           const int32_t* longlist,
                                                           int ntiles_c, unsigned char* lds,
                                                           bool staged, int bid_, int nblk_,
-                                                          bool inline_tail = true) {
+                                                          bool inline_tail = true,
+                                                          bool huge = false) {
   // lds: kWin x (int64 + int32) bytes, and with `staged` another
   // kSortCap x (int64 + int32) bytes that hold a whole row
   int64_t* acc = (int64_t*)lds;
@@ -695,7 +736,8 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
   int32_t* stk = (int32_t*)(stv + kSortCap);
   __shared__ int32_t smi[kBlock / 64];
   __shared__ int64_t sml[kBlock / 64];
-  const int32_t nlong = ctrl->nlong;
+  // huge: the rows that the row kernel listed for one block each
+  const int32_t nlong = huge ? ctrl->nhuge : ctrl->nlong;
   for (int32_t i = bid_; i < nlong; i += nblk_) {
     const int32_t c = longlist[i];
     int L;
@@ -740,12 +782,152 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
     if (threadIdx.x == 0) {
       cnt[c] = k;
       atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
-      atomicAdd((unsigned long long*)&ctrl->long_out, (unsigned long long)k);
+      atomicAdd((unsigned long long*)(huge ? &ctrl->huge_out : &ctrl->long_out),
+                (unsigned long long)k);
     }
   }
   if (!inline_tail) return;
   __syncthreads();
   b_tile_scan(ctrl, tile_cnt, ntiles_c);
+}
+
+// One coarse row of 64 < L <= kLongCap candidates on a level with fewer
+// than kPackMaxNc coarse vertices, by one wave.  Candidate j (a position in
+// the concatenated member rows) becomes the key (coarse id << kPackIdBits) | j,
+// unique within the row, or INT_MAX for the internal edge; the keys are
+// sorted in the wave's LDS (sk: next_pow2(L) keys, at least 512 slots), and
+// each run of one coarse id is summed by the lane that holds its head,
+// reading the weights at the runs' positions.  Writes the row's distinct
+// coarse neighbours to ok / ov and returns their count (in every lane).
+__device__ __forceinline__ int wave_row_packed(const LevelView& lv, const int32_t* cmap,
+                                               const CoarseRowLoader& ld, int32_t c, int L,
+                                               int32_t* sk, int32_t* ok, int64_t* ov) {
+  const int lane = lane_id();
+  constexpr int32_t kPos = (1 << kPackIdBits) - 1;
+  const int P2 = next_pow2(L);  // >= 128: L > 64
+  const int32_t ebase = ld.d0 > 0 ? ld.e0 : ld.e1;  // an entry of the row (L > 0)
+  // keys, eight candidates per lane in flight; every load is made, at a
+  // valid index (slots past the row read an entry of it and are dropped), so
+  // that none waits behind a branch
+  for (int j0 = 0; j0 < P2; j0 += 512) {
+    int32_t e[8], y[8], x[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int j = j0 + u * 64 + lane;
+      e[u] = j < L ? (j < ld.d0 ? ld.e0 + j : ld.e1 + (j - ld.d0)) : ebase;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) y[u] = lv.adj[e[u]];
+#pragma unroll
+    for (int u = 0; u < 8; u++) x[u] = cmap[y[u]];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int j = j0 + u * 64 + lane;
+      sk[j] = (j < L && x[u] != c) ? ((x[u] << kPackIdBits) | j) : INT_MAX;
+    }
+  }
+  wave_sync();
+  wave_sort_keys(sk, P2);
+  // lane t owns the sorted slots [t * per, (t + 1) * per)
+  const int per = P2 >> 6;
+  const int s0 = lane * per;
+  int heads = 0;
+  for (int j = s0; j < s0 + per; j++) {
+    const int32_t k = sk[j];
+    if (k == INT_MAX) break;
+    if (j == 0 || (sk[j - 1] >> kPackIdBits) != (k >> kPackIdBits)) heads++;
+  }
+  int incl = heads;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  int pos = incl - heads;  // output slot of this lane's first head
+  // weights of the own slots, eight loads in flight; the sum of the slots
+  // before the first head continues the run of an earlier lane
+  int64_t lead = 0, acc = 0;
+  int32_t cur = -1;
+  bool seen_head = false;
+  for (int j = s0; j < s0 + per; j += 8) {
+    int32_t kk[8];
+    int64_t ww[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) kk[u] = j + u < s0 + per ? sk[j + u] : INT_MAX;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int32_t q = kk[u] != INT_MAX ? (kk[u] & kPos) : 0;
+      const int32_t e = q < ld.d0 ? ld.e0 + q : ld.e1 + (q - ld.d0);
+      ww[u] = lv.w[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      if (kk[u] == INT_MAX) continue;
+      const int32_t cid = kk[u] >> kPackIdBits;
+      const bool head = (j + u == 0) || (sk[j + u - 1] >> kPackIdBits) != cid;
+      if (head) {
+        if (seen_head) {
+          ok[pos] = cur;
+          ov[pos] = acc;
+          pos++;
+        }
+        seen_head = true;
+        cur = cid;
+        acc = ww[u];
+      } else if (seen_head) {
+        acc += ww[u];
+      } else {
+        lead += ww[u];
+      }
+    }
+  }
+  // the last run of a lane may continue into the next lanes: add their lead
+  // sums up to and including the first lane that holds a head
+  const bool open = seen_head;
+  const int empty = s0 >= L || sk[s0] == INT_MAX;  // holds no candidate
+  bool more = true;
+  for (int o = 1; o < 64; o++) {
+    const int64_t l2 = __shfl_down(lead, o, 64);
+    const int h2 = __shfl_down(heads, o, 64);
+    const int e2 = __shfl_down(empty, o, 64);
+    if (open && more && lane + o < 64 && !e2) {
+      acc += l2;
+      if (h2 > 0) more = false;
+    } else {
+      more = false;
+    }
+    if (!__any(open && more)) break;
+  }
+  if (seen_head) {
+    ok[pos] = cur;
+    ov[pos] = acc;
+  }
+  wave_sync();  // the keys are reused by the next row
+  return total;
+}
+
+// Rows of kWaveCap < L <= kLongCap candidates on a level with fewer than
+// kPackMaxNc coarse vertices: one wave per row (sk: the wave's kLongCap keys
+// of LDS).
+__device__ __forceinline__ void b_contract_longw(LevelView lv, const int32_t* cmap,
+                                                 const int32_t* cmem0, const int32_t* cmem1,
+                                                 const int64_t* toff, Ctrl* ctrl, int32_t* tmpk,
+                                                 int64_t* tmpv, int32_t* cnt, int64_t* tile_cnt,
+                                                 const int32_t* longlist, int32_t* sk, int wid,
+                                                 int nw) {
+  const int32_t nlong = ctrl->nlong;
+  for (int32_t i = wid; i < nlong; i += nw) {
+    const int32_t c = longlist[i];
+    int L;
+    const CoarseRowLoader ld = coarse_loader(lv, cmap, cmem0, cmem1, c, &L);
+    const int total = wave_row_packed(lv, cmap, ld, c, L, sk, tmpk + toff[c], tmpv + toff[c]);
+    if (lane_id() == 0) {
+      cnt[c] = total;
+      atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)total);
+      atomicAdd((unsigned long long*)&ctrl->long_out, (unsigned long long)total);
+    }
+  }
 }
 
 __device__ __forceinline__ void b_contract_compact(const Ctrl* ctrl,

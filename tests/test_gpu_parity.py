@@ -372,3 +372,44 @@ def test_random_mixed_sweep(gp, seed):
                   init_trials=int(rng.choice([1, 4, 16])), seed=int(rng.integers(0, 1000)))
         ref, got, res, _ = run_both(gp, g, trace=False, **kw)
         assert_same(ref, got, res)
+
+
+def dense_random(n, deg, seed, name):
+    """Random graph with about deg neighbours per vertex, drawn as edge lists
+    (the triangle form of random_graph is too large at this size)."""
+    rng = np.random.default_rng(seed)
+    m = n * deg // 2
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    keep = src != dst
+    w = rng.integers(1, 10**6, keep.sum()).astype(np.int64)
+    vw = rng.integers(1, 100, (n, 2)).astype(np.int64)
+    return dagen.to_csr(n, src[keep], dst[keep], w, vw, name)
+
+
+def test_long_rows_one_wave_each(gp):
+    """Coarse rows of 513..4,096 candidates on levels with few coarse vertices:
+    the one-wave packed-key sort.  Every level against the oracle."""
+    g = dense_random(6000, 420, 21, "dense6000")
+    check_hierarchy(gp, g, coarsen_to=64, ratio=(1, 3))
+    assert_same(*run_both(gp, g, coarsen_to=64, ratio=(1, 3)))
+
+
+def test_long_rows_beyond_packed_ids(gp):
+    """Long coarse rows on a level with more than 2^19 - 1 coarse vertices,
+    where the packed key does not fit: rows beyond one wave's LDS sort take
+    the one-block form, rows of 65..512 candidates the (key, value) wave sort."""
+    n = 1_100_000
+    rng = np.random.default_rng(8)
+    src = rng.integers(0, n, 3 * n).astype(np.int32)
+    dst = rng.integers(0, n, 3 * n).astype(np.int32)
+    hubs = rng.choice(n, 2300, replace=False).astype(np.int32)
+    hs = np.concatenate([np.repeat(hubs[:300], 900), np.repeat(hubs[300:], 150)])
+    hd = rng.integers(0, n, len(hs)).astype(np.int32)
+    src, dst = np.concatenate([src, hs]), np.concatenate([dst, hd])
+    keep = src != dst
+    w = rng.integers(1, 1000, keep.sum()).astype(np.int64)
+    vw = rng.integers(1, 50, (n, 2)).astype(np.int64)
+    g = dagen.to_csr(n, src[keep], dst[keep], w, vw, "hubs1.1m")
+    check_hierarchy(gp, g)
+    assert_same(*run_both(gp, g))
