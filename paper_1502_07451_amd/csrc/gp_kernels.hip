@@ -476,7 +476,9 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
     // rows of kWaveCap..kLongCap candidates, one wave each; ten waves fit a
     // compute unit's LDS
-    const int gw = grid_for(nc_max, 64, 2560) < 256 ? 256 : grid_for(nc_max, 64, 2560);
+    // every coarse row may be long: up to one wave per row, at most the ten
+    // waves per compute unit that the LDS holds
+    const int gw = nc_max < 2560 ? (nc_max > 0 ? nc_max : 1) : 2560;
     k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
                                       sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist);
   }
@@ -491,7 +493,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     ProfScope ps(PK_CONTRACT_HUGE, 0, 0.0, s);
     // the rest of the long rows (sc.prop is free during contraction: it holds
     // their list), one block each
-    const int glong = grid_for(nc_max, 512, 1024) < 64 ? 64 : grid_for(nc_max, 512, 1024);
+    // up to one block per row; one block per compute unit fits the LDS
+    const int glong = nc_max < 512 ? (nc_max > 0 ? nc_max : 1) : 512;
     k_contract_huge<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl,
                                                sc.tmpk, sc.tmpv, sc.cnt, sc.tile_cnt, sc.prop,
                                                ntc1);
