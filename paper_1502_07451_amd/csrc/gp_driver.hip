@@ -94,6 +94,8 @@ struct gp_graph {
   DBuf<int32_t> prop, tile_lead, cmem0, cmem1, cnt, tmpk, longlist;
   DBuf<int64_t> tile_ub, toff, tile_cnt, tmpv;
   DBuf<int64_t> partials;  // <= 5 per block of a multi-block reduction (grids of <= 4096)
+  DBuf<int64_t> r_ext, r_inn;  // refinement: per-vertex external / internal weight
+  DBuf<int32_t> r_mark;        // refinement: vertices moved by the current pass
   DBuf<Cand> list;
   // initial bisection scratch
   DBuf<int64_t> i_tot, i_conn, i_res;
@@ -136,7 +138,8 @@ struct gp_graph {
            tile_ub.ensure(n1 / kTileV + 2) && cmem0.ensure(n1) && cmem1.ensure(n1) &&
            toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
            tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1) &&
-           partials.ensure(5 * 4096);
+           partials.ensure(5 * 4096) && r_ext.ensure(n1) && r_inn.ensure(n1) &&
+           r_mark.ensure(n1);
   }
   bool ensure_init(int32_t nl, int K) {
     const int64_t kn = (int64_t)K * (nl > 0 ? nl : 1);
@@ -162,6 +165,7 @@ struct gp_graph {
     prop.release(); tile_lead.release(); cmem0.release(); cmem1.release(); cnt.release();
     tmpk.release(); longlist.release(); tile_ub.release(); toff.release(); tile_cnt.release();
     tmpv.release(); list.release(); partials.release();
+    r_ext.release(); r_inn.release(); r_mark.release();
     i_tot.release(); i_conn.release(); i_res.release(); i_ctl.release(); i_part.release();
     i_adjc.release(); i_list.release();
     m_ha.release(); m_hb.release(); m_inv.release(); m_score.release(); m_order.release();
@@ -216,8 +220,8 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
       if (r.kind == PK_CONTRACT_HUGE) r.bytes = 16 * hi + 12 * ho;
       if (r.kind == PK_CONTRACT_COMPACT) r.bytes = 24 * mc + 16 * nc + 4;
     }
-    if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_SETTLE ||
-                        r.kind == PK_REFINE_APPLY))
+    if (!coarsening && (r.kind == PK_REFINE_GAIN || r.kind == PK_REFINE_SCAN ||
+                        r.kind == PK_REFINE_SETTLE || r.kind == PK_REFINE_APPLY))
       r.executed = r.idx < h.lvl_pass[level] ? 1 : 0;
   }
 }
@@ -588,13 +592,14 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
       Level* c = g->lv[l + 1];
       g->prof.level = l;
       g->prof.idx = 0;
-      LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, s));
+      const RefArrays ra{g->r_ext.p, g->r_inn.p, g->r_mark.p};
+      LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, ra.mark, s));
       const int tw = team_width_for(f->n, f->nnz);
       const LevelView fv = f->view(bal);
       for (int p = 0; p < P; p++) {
         g->prof.idx = p;
         LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
-                                &g->ctrl->lvl_pass[l], s));
+                                &g->ctrl->lvl_pass[l], p, P, ra, s));
       }
       if ((e2 = record(l, false, tr)) != GP_OK) return e2;
     }

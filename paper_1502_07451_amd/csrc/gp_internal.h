@@ -55,6 +55,10 @@ struct RefCtl {
   int64_t total_moves;
   int64_t last_cut;
   uint32_t ctr_gain, ctr_apply;   // last-block counters
+  // the pass just finished (kept for the neighbour updates that follow it)
+  uint32_t last_ncand;            // candidates listed
+  int32_t last_d;                 // side the moved vertices joined
+  int64_t last_moved_n;           // vertices moved
 };
 
 struct Ctrl {

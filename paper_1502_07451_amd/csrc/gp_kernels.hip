@@ -160,9 +160,26 @@ __global__ __launch_bounds__(kBlock) void k_contract_compact(const Ctrl* ctrl,
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list,
-                                                        int64_t* partials) {
+                                                        int64_t* partials, int64_t* sext,
+                                                        int64_t* sinn) {
   __shared__ SelShared sel;
-  b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x, false);
+  b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x, false,
+                    sext, sinn);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_scan(int32_t n, const int8_t* part,
+                                                        const int64_t* b, const int64_t* sext,
+                                                        const int64_t* sinn, RefCtl* rc,
+                                                        Cand* list, int64_t* partials) {
+  b_refine_scan(n, part, b, sext, sinn, rc, list, partials, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <int TW>
+__global__ __launch_bounds__(kBlock) void k_refine_delta(LevelView lv, const int8_t* part,
+                                                         const int32_t* mark, int64_t* sext,
+                                                         int64_t* sinn, const RefCtl* rc,
+                                                         const Cand* list, int p) {
+  b_refine_delta<TW>(lv, part, mark, sext, sinn, rc, list, p, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_decide(int32_t n, RefCtl* rc, const Cand* list,
@@ -172,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_decide(int32_t n, RefCtl* rc,
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_apply(int8_t* part, RefCtl* rc,
-                                                         const Cand* list, int32_t* pass_out) {
-  b_refine_apply(part, rc, list, pass_out, (int)blockIdx.x, (int)gridDim.x, false);
+                                                         const Cand* list, int32_t* pass_out,
+                                                         int32_t* mark) {
+  b_refine_apply(part, rc, list, pass_out, (int)blockIdx.x, (int)gridDim.x, false, mark);
 }
 
 __global__ void k_refine_finish(RefCtl* rc, int32_t* pass_out) { b_refine_finish(rc, pass_out); }
@@ -181,15 +199,15 @@ __global__ void k_refine_finish(RefCtl* rc, int32_t* pass_out) { b_refine_finish
 __global__ __launch_bounds__(kBlock) void k_refine_settle(int32_t n, int8_t* part, RefCtl* rc,
                                                           const Cand* list,
                                                           const int64_t* partials, int nparts,
-                                                          int32_t* pass_out) {
+                                                          int32_t* pass_out, int32_t* mark) {
   __shared__ SelShared sel;
-  b_refine_settle(n, part, rc, list, partials, nparts, &sel, pass_out);
+  b_refine_settle(n, part, rc, list, partials, nparts, &sel, pass_out, mark);
 }
 
 __global__ __launch_bounds__(kBlock) void k_project(int32_t n, const int32_t* cmap,
                                                     const int8_t* cpart, int8_t* part, RefCtl* rc,
-                                                    int npass) {
-  b_project(n, cmap, cpart, part, rc, npass, (int)blockIdx.x, (int)gridDim.x);
+                                                    int npass, int32_t* mark) {
+  b_project(n, cmap, cpart, part, rc, npass, (int)blockIdx.x, (int)gridDim.x, mark);
 }
 
 __global__ void k_start_level(RefCtl* rc, int npass) {
@@ -283,8 +301,8 @@ const char* const kProfNames[PK_N] = {
     "k_match_round", "k_match_settle", "k_hub", "k_twohop", "k_iso", "k_contract_count",
     "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_huge",
     "k_contract_compact", "k_init_tot",
-    "k_init_trials", "k_refine_gain", "k_refine_settle", "k_refine_apply", "k_project",
-    "k_final_stats"};
+    "k_init_trials", "k_refine_gain", "k_refine_scan", "k_refine_delta", "k_refine_settle",
+    "k_refine_apply", "k_project", "k_final_stats"};
 
 thread_local Prof* g_prof = nullptr;
 
@@ -514,52 +532,81 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
 // the gain launch; *grid_out = its block count (the number of partials)
 template <int TW>
 static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* list,
-                    int64_t* partials, int* grid_out, hipStream_t s) {
+                    int64_t* partials, const RefArrays& ra, int* grid_out, hipStream_t s) {
   // one row per team: the row loads of all vertices are in flight at once
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
-  ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 1.0 * lv.n, s);
-  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials);
+  ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 17.0 * lv.n, s);
+  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials, ra.ext, ra.inn);
   KCHECK();
   *grid_out = grid;
   return true;
 }
 
-bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
-                        int64_t* partials, int tw,
-                        int32_t* pass_out, hipStream_t s) {
-  bool ok;
-  int grid = 0;
-  switch (tw) {
-    case 4: ok = gain_tw<4>(lv, part, rc, list, partials, &grid, s); break;
-    case 8: ok = gain_tw<8>(lv, part, rc, list, partials, &grid, s); break;
-    case 16: ok = gain_tw<16>(lv, part, rc, list, partials, &grid, s); break;
-    case 32: ok = gain_tw<32>(lv, part, rc, list, partials, &grid, s); break;
-    default: ok = gain_tw<64>(lv, part, rc, list, partials, &grid, s); break;
-  }
-  if (!ok) return false;
-  if (lv.n <= kSettleMax) {
-    // decision, moves and pass bookkeeping in one single-block launch
-    ProfScope ps(PK_REFINE_SETTLE, 0, 0.0, s);
-    k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out);
-    KCHECK();
-    return true;
-  }
-  k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
-  KCHECK();
-  {
-    ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
-    k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list, pass_out);
-  }
-  KCHECK();
-  k_refine_finish<<<1, 64, 0, s>>>(rc, pass_out);
+template <int TW>
+static bool delta_tw(const LevelView& lv, const int8_t* part, const RefCtl* rc, const Cand* list,
+                     const RefArrays& ra, int p, hipStream_t s) {
+  // one team per listed candidate (at most n of them)
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock, 2048);
+  ProfScope ps(PK_REFINE_DELTA, TW, 0.0, s);
+  k_refine_delta<TW><<<grid, kBlock, 0, s>>>(lv, part, ra.mark, ra.ext, ra.inn, rc, list, p);
   KCHECK();
   return true;
 }
 
+bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                        int64_t* partials, int tw, int32_t* pass_out, int p, int npass,
+                        const RefArrays& ra, hipStream_t s) {
+  bool ok;
+  int grid = 0;
+  if (p == 0) {
+    // the first pass of a level reads the rows and keeps every vertex's
+    // external and internal weight
+    switch (tw) {
+      case 4: ok = gain_tw<4>(lv, part, rc, list, partials, ra, &grid, s); break;
+      case 8: ok = gain_tw<8>(lv, part, rc, list, partials, ra, &grid, s); break;
+      case 16: ok = gain_tw<16>(lv, part, rc, list, partials, ra, &grid, s); break;
+      case 32: ok = gain_tw<32>(lv, part, rc, list, partials, ra, &grid, s); break;
+      default: ok = gain_tw<64>(lv, part, rc, list, partials, ra, &grid, s); break;
+    }
+    if (!ok) return false;
+  } else {
+    grid = grid_for(lv.n, kBlock);
+    ProfScope ps(PK_REFINE_SCAN, 0, 25.0 * lv.n, s);
+    k_refine_scan<<<grid, kBlock, 0, s>>>(lv.n, part, lv.b, ra.ext, ra.inn, rc, list, partials);
+    KCHECK();
+  }
+  if (lv.n <= kSettleMax) {
+    // decision, moves and pass bookkeeping in one single-block launch
+    ProfScope ps(PK_REFINE_SETTLE, 0, 0.0, s);
+    k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out,
+                                         ra.mark);
+    KCHECK();
+  } else {
+    k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
+    KCHECK();
+    {
+      ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
+      k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list,
+                                                                         pass_out, ra.mark);
+    }
+    KCHECK();
+    k_refine_finish<<<1, 64, 0, s>>>(rc, pass_out);
+    KCHECK();
+  }
+  if (p + 1 >= npass) return true;  // no pass reads the weights after the last one
+  switch (tw) {
+    case 4: return delta_tw<4>(lv, part, rc, list, ra, p, s);
+    case 8: return delta_tw<8>(lv, part, rc, list, ra, p, s);
+    case 16: return delta_tw<16>(lv, part, rc, list, ra, p, s);
+    case 32: return delta_tw<32>(lv, part, rc, list, ra, p, s);
+    default: return delta_tw<64>(lv, part, rc, list, ra, p, s);
+  }
+}
+
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
-                    int npass, hipStream_t s) {
-  ProfScope ps(PK_PROJECT, 0, 6.0 * n, s);
-  k_project<<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, cmap, cpart, part, rc, npass);
+                    int npass, int32_t* mark, hipStream_t s) {
+  ProfScope ps(PK_PROJECT, 0, 10.0 * n, s);
+  k_project<<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, cmap, cpart, part, rc, npass, mark);
   KCHECK();
   return true;
 }

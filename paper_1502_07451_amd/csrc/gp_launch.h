@@ -40,8 +40,8 @@ enum ProfKind {
   PK_MATCH_ROUND, PK_MATCH_SETTLE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
   PK_CONTRACT_MAP, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_HUGE, PK_CONTRACT_COMPACT,
   PK_INIT_TOT,
-  PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_SETTLE, PK_REFINE_APPLY, PK_PROJECT,
-  PK_FINAL_STATS, PK_N
+  PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_SCAN, PK_REFINE_DELTA, PK_REFINE_SETTLE,
+  PK_REFINE_APPLY, PK_PROJECT, PK_FINAL_STATS, PK_N
 };
 extern const char* const kProfNames[PK_N];
 
@@ -83,12 +83,22 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
 bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, const Scratch& sc,
                        int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
                        hipStream_t s);
+// per-vertex state of the passes of one level, sized for level 0
+struct RefArrays {
+  int64_t* ext;   // n: weight to the other side, kept up to date across passes
+  int64_t* inn;   // n: weight to the own side
+  int32_t* mark;  // n: p + 1 for the vertices moved by pass p, cleared by the projection
+};
+
+// Pass p (of npass) of a level: the first pass computes every vertex's
+// external and internal weight from the rows, later ones read them; the
+// moves' effect on those weights is applied after each pass but the last.
 // partials: 4 int64 per block of the gain kernel (grids are capped at 4096)
 bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
-                        int64_t* partials, int tw,
-                        int32_t* pass_out, hipStream_t s);
+                        int64_t* partials, int tw, int32_t* pass_out, int p, int npass,
+                        const RefArrays& ra, hipStream_t s);
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
-                    int npass, hipStream_t s);
+                    int npass, int32_t* mark, hipStream_t s);
 bool launch_start_level(RefCtl* rc, int npass, hipStream_t s);
 // partials: 5 int64 per block (grids are capped at 4096)
 bool launch_final_stats(const LevelView& lv, const int64_t* vc, const int64_t* vg,

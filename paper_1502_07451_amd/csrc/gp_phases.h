@@ -1041,6 +1041,9 @@ __device__ __forceinline__ bool admitted(const RefCtl& r, const Cand& c) {
 
 __device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_b, int64_t moved_n) {
   const int s = rc->s, d = 1 - s;
+  rc->last_ncand = rc->ncand;
+  rc->last_d = d;
+  rc->last_moved_n = moved_n;
   rc->pw[s] -= moved_b;
   rc->pw[d] += moved_b;
   rc->total_moves += moved_n;
@@ -1061,7 +1064,9 @@ template <int TW>
 __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list, SelShared* sel,
                                                         int64_t* partials, int bid_, int nblk_,
-                                                        bool inline_tail = true) {
+                                                        bool inline_tail = true,
+                                                        int64_t* sext = nullptr,
+                                                        int64_t* sinn = nullptr) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   int mode, s;
@@ -1113,6 +1118,10 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
       if (lane == 0) {
         const int64_t gain = ext - in;
         ext_acc += ext;
+        if (sext) {
+          sext[v] = ext;
+          sinn[v] = in;
+        }
         cand = pv == s && (mode == 1 || gain > 0);
         if (cand) {
           c.gain = gain;
@@ -1206,7 +1215,8 @@ constexpr int32_t kSettleMax = 65536;
 
 __device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl* rc,
                                                 const Cand* list, const int64_t* partials,
-                                                int nparts, SelShared* sel, int32_t* pass_out) {
+                                                int nparts, SelShared* sel, int32_t* pass_out,
+                                                int32_t* mark = nullptr) {
   __shared__ int64_t sms[kBlock / 64];
   if (rc->done) return;
   b_refine_decide(n, rc, list, partials, nparts, sel);
@@ -1229,6 +1239,7 @@ __device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl*
         const int64_t i = i0 + (int64_t)u * kBlock;
         if (i < nc && admitted(r, c[u])) {
           part[c[u].v] = (int8_t)d;
+          if (mark) mark[c[u].v] = r.pass + 1;
           mb += c[u].b;
           mn++;
         }
@@ -1253,7 +1264,8 @@ __device__ __forceinline__ void b_refine_finish(RefCtl* rc, int32_t* pass_out) {
 
 __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
                                                          const Cand* list, int32_t* pass_out, int bid_, int nblk_,
-                                                         bool inline_tail = true) {
+                                                         bool inline_tail = true,
+                                                         int32_t* mark = nullptr) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   const RefCtl r = *rc;
@@ -1264,6 +1276,7 @@ __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
     const Cand c = list[i];
     if (admitted(r, c)) {
       part[c.v] = (int8_t)d;
+      if (mark) mark[c.v] = r.pass + 1;
       mb += c.b;
       mn++;
     }
@@ -1290,15 +1303,113 @@ __device__ __forceinline__ void start_level(RefCtl* rc, int npass) {
 
 __device__ __forceinline__ void b_project(int32_t n, const int32_t* cmap,
                                                     const int8_t* cpart, int8_t* part, RefCtl* rc,
-                                                    int npass, int bid_, int nblk_) {
+                                                    int npass, int bid_, int nblk_,
+                                                    int32_t* mark = nullptr) {
   for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
-       u += (int64_t)nblk_ * kBlock)
+       u += (int64_t)nblk_ * kBlock) {
     part[u] = cpart[cmap[u]];
+    if (mark) mark[u] = 0;
+  }
   if (bid_ == 0 && threadIdx.x == 0) start_level(rc, npass);
 }
 
 __device__ __forceinline__ void b_start_level(RefCtl* rc, int npass, int bid_, int nblk_) {
   if (threadIdx.x == 0) start_level(rc, npass);
+}
+
+// Later passes of a level read the per-vertex external and internal
+// weights kept in sext / sinn instead of the rows: one vertex per thread,
+// the same candidates and per-block partials as the gain kernel.
+__device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, const int64_t* b,
+                                              const int64_t* sext, const int64_t* sinn,
+                                              RefCtl* rc, Cand* list, int64_t* partials,
+                                              int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  if (rc->done) return;
+  int mode, s;
+  plan_pass(*rc, &mode, &s);
+  int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+  const int64_t stride = (int64_t)nblk_ * kBlock;
+  // every thread runs the same number of iterations for the wave ballot
+  const int64_t iters = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; it++) {
+    const int64_t v = (int64_t)bid_ * kBlock + threadIdx.x + it * stride;
+    bool cand = false;
+    Cand c;
+    c.pad = 0;
+    if (v < n) {
+      const int8_t pv = part[v];
+      const int64_t ext = sext[v], in = sinn[v], bv = b[v];
+      const int64_t gain = ext - in;
+      ext_acc += ext;
+      cand = pv == s && (mode == 1 || gain > 0);
+      if (cand) {
+        c.gain = gain;
+        c.b = bv;
+        c.v = (int32_t)v;
+        cb += bv;
+        gmn = gain < gmn ? gain : gmn;
+        gmx = gain > gmx ? gain : gmx;
+      }
+    }
+    append_cand(cand, c, list, &rc->ncand);
+  }
+  ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+  cb = block_sum<kBlock, int64_t>(cb, sml);
+  gmn = block_min<kBlock, int64_t>(gmn, sml);
+  gmx = block_max<kBlock, int64_t>(gmx, sml);
+  if (threadIdx.x == 0) {
+    partials[4 * bid_ + 0] = ext_acc;
+    partials[4 * bid_ + 1] = cb;
+    partials[4 * bid_ + 2] = gmn;
+    partials[4 * bid_ + 3] = gmx;
+  }
+}
+
+// After pass p moved the vertices marked p + 1 (all from one side to d):
+// every unmoved neighbour x of a moved vertex u sees the edge change sides
+// (internal <-> external, exact integer atomics, so the order does not
+// matter); a moved u swaps its external and internal weights, except for
+// the edges to other moved vertices, which stay internal.  One team per
+// listed candidate; unmoved candidates are skipped.
+template <int TW>
+__device__ __forceinline__ void b_refine_delta(LevelView lv, const int8_t* part,
+                                               const int32_t* mark, int64_t* sext, int64_t* sinn,
+                                               const RefCtl* rc, const Cand* list, int p,
+                                               int bid_, int nblk_) {
+  // pass p did not run, moved nothing, or was the level's last
+  if (rc->pass != p + 1 || rc->last_moved_n == 0 || rc->done) return;
+  const uint32_t nlist = rc->last_ncand;
+  const int d = rc->last_d;
+  const int32_t stamp = p + 1;
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t i = team; i < nlist; i += nteams) {
+    const int32_t u = list[i].v;
+    if (mark[u] != stamp) continue;  // the whole team skips together
+    int64_t corr = 0;
+    const int32_t e1 = lv.xadj[u + 1];
+    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
+      const int32_t x = lv.adj[e];
+      const int64_t w = lv.w[e];
+      if (mark[x] == stamp) {
+        corr += w;
+      } else if (part[x] == d) {
+        atomicAdd((unsigned long long*)&sext[x], (unsigned long long)(-w));
+        atomicAdd((unsigned long long*)&sinn[x], (unsigned long long)w);
+      } else {
+        atomicAdd((unsigned long long*)&sext[x], (unsigned long long)w);
+        atomicAdd((unsigned long long*)&sinn[x], (unsigned long long)(-w));
+      }
+    }
+    corr = team_sum<TW>(corr);
+    if (lane == 0) {
+      const int64_t e0 = sext[u], i0 = sinn[u];
+      sext[u] = i0 - corr;
+      sinn[u] = e0 + corr;
+    }
+  }
 }
 
 // cut (as sum of ext), loads and times of the final assignment
