@@ -173,6 +173,22 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
       if (lane == 0) prop_cur[u] = -1;
       continue;
     }
+    if (round > 0) {
+      // The neighbours free at this round's start are a subset of those free
+      // at the previous round's start, and the weight cap does not change:
+      // if u's previous choice t is still free, t is still the best, and if
+      // u had no choice it still has none.  Only the others rescan the row.
+      const int32_t t = prop_prev[u];
+      bool keep = t < 0;
+      if (!keep) {
+        const int32_t mt = match[t], pt = prop_prev[t];
+        keep = mt == -1 && !(pt >= 0 && prop_prev[pt] == t);
+      }
+      if (keep) {
+        if (lane == 0) prop_cur[u] = t;
+        continue;
+      }
+    }
     const bool capcheck = bu + maxb > cap;
     int64_t bw = -1;
     int32_t bv = -1;
