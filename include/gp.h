@@ -200,6 +200,26 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
                              const int64_t* vwgt, const gp_options* o, int8_t* part,
                              gp_result* res);
 void gp_batch_destroy(gp_batch* b);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gp_partition_batch with
+ * no allocation of any kind.  Its scratch is one fixed 64 MiB device array
+ * per GPU, held from the first call on that GPU until the process ends.
+ * All pointers are device memory, res included (G records); the call only
+ * queues two kernels on `stream` and returns without waiting.  Graphs are
+ * taken in input order.  nmax / nnzmax bound every graph's vertex and entry
+ * count (a graph beyond them gets status GP_EINVAL); ntot / nnztot are the
+ * totals voff[G] and eoff[G].  When the per-workgroup scratch for these
+ * bounds plus the level arena estimate (3 x (57 ntot + 12 nnztot) +
+ * 8192 G + 1 MiB bytes) exceed the 64 MiB, the call returns GP_ENOMEM and
+ * queues nothing; a graph whose levels still overrun the arena gets status
+ * GP_ENOMEM (no retry).  Calls that overlap on one GPU share its array and
+ * race: run them on one stream.  GP_LEARNED is not available (GP_EMODEL). */
+gp_status gp_partition_batch_noalloc(int32_t G, const int64_t* voff, const int64_t* eoff,
+                                     const int32_t* xadj, const int32_t* adjncy,
+                                     const int64_t* adjwgt, const int64_t* vwgt,
+                                     const gp_options* o, int32_t nmax, int32_t nnzmax,
+                                     int64_t ntot, int64_t nnztot, int8_t* part,
+                                     gp_result* res, void* stream);
 /* Autotuner of the batched path: runs gp_partition_batch with each of 18
  * configurations (1, 2 or 3 persistent workgroups per compute unit x 1, 2
  * or 4 graphs per queue pop x largest-first or input order), checks that

@@ -94,6 +94,10 @@ def _load():
     lib.gp_partition_batch.restype = ctypes.c_int
     lib.gp_batch_destroy.argtypes = [vp]
     lib.gp_batch_destroy.restype = None
+    lib.gp_partition_batch_noalloc.argtypes = [i32, vp, vp, vp, vp, vp, vp,
+                                               ctypes.POINTER(Options), i32, i32, i64, i64, vp,
+                                               vp, vp]
+    lib.gp_partition_batch_noalloc.restype = ctypes.c_int
     lib.gp_model_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.gp_model_create.restype = ctypes.c_int
     lib.gp_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
@@ -392,6 +396,45 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def partition_batch_noalloc(G, voff, eoff, xadj, adjncy, adjwgt, vwgt, opts=None, part=None,
+                            res=None, nmax=None, nnzmax=None, ntot=None, nnztot=None,
+                            stream=None):
+    """gp_partition_batch_noalloc: the batched partition with the library's
+    fixed device scratch, queued on `stream` without waiting.  Device
+    tensors as in Batch.partition; res is a device uint8 tensor of
+    G * sizeof(Result) bytes.  The size bounds default to the exact ones
+    (read from voff / eoff).  Returns (part, res); results_from_device turns
+    res into Result records once the stream has finished."""
+    import torch
+    opts = opts or options()
+    if part is None:
+        part = torch.empty(max(int(vwgt.numel()) // 2, 1), dtype=torch.int8, device=xadj.device)
+    if res is None:
+        res = torch.empty(max(G, 1) * ctypes.sizeof(Result), dtype=torch.uint8,
+                          device=xadj.device)
+    if None in (nmax, nnzmax, ntot, nnztot):
+        hv, he = voff.cpu().numpy(), eoff.cpu().numpy()
+        nmax = (int(np.diff(hv).max()) if G else 0) if nmax is None else nmax
+        nnzmax = (int(np.diff(he).max()) if G else 0) if nnzmax is None else nnzmax
+        ntot = int(hv[-1]) if ntot is None else ntot
+        nnztot = int(he[-1]) if nnztot is None else nnztot
+    st = _lib.gp_partition_batch_noalloc(int(G), _ptr(voff), _ptr(eoff), _ptr(xadj),
+                                         _ptr(adjncy), _ptr(adjwgt), _ptr(vwgt),
+                                         ctypes.byref(opts), int(nmax), int(nnzmax), int(ntot),
+                                         int(nnztot), _ptr(part), _ptr(res),
+                                         stream if stream is not None else _current_stream())
+    if st != OK:
+        raise GPError(st, "gp_partition_batch_noalloc")
+    return part, res
+
+
+def results_from_device(res, G):
+    """Result records from a device tensor filled by partition_batch_noalloc."""
+    raw = res.cpu().numpy().tobytes()
+    arr = (Result * max(G, 1)).from_buffer_copy(raw[:ctypes.sizeof(Result) * max(G, 1)])
+    return list(arr[:G])
 
 
 def batch_to_device(b, device="cuda"):

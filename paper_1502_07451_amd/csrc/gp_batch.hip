@@ -11,6 +11,8 @@
 // writes only its own data, with integer arithmetic.
 #include <string.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <chrono>
 #include <new>
@@ -215,6 +217,11 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   const int64_t* w = a.w + e0;
   const int64_t* vwgt = a.vwgt + 2 * v0;
   zero_ctrl(ctrl);
+  if (n < 0 || nnz < 0 || n > a.nmax || nnz > a.nnzmax) {
+    // outside the bounds the workgroup scratch was laid out for
+    write_status(a, g, GP_EINVAL);
+    return;
+  }
   if (n == 0) {
     if (threadIdx.x == 0) {
       gp_result r;
@@ -516,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
     __syncthreads();
     if (first >= a.G) break;
     const int last = first + a.chunk < a.G ? first + a.chunk : a.G;
-    for (int i = first; i < last; i++) batch_graph(a, a.order[i], ws, lds, &sel, &srf);
+    for (int i = first; i < last; i++) batch_graph(a, a.order ? a.order[i] : i, ws, lds, &sel, &srf);
   }
 }
 
@@ -916,6 +923,114 @@ gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const i
   // leave the caller the chosen configuration's (identical) outputs
   st = gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part, res);
   return st;
+}
+
+// ------------------------------------------------ allocation-free batch
+// Device scratch of gp_partition_batch_noalloc: one fixed array per GPU
+// (the code object's own copy on each device), held until the process ends.
+// Host code never uses the array's name as an address: the device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t kNoAllocBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoAllocDevices];
+int g_noalloc_cus[kNoAllocDevices];
+
+// the current device's scratch address and compute-unit count
+gp_status noalloc_setup(unsigned char** ptr, int* cus) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) {
+    (void)hipGetLastError();
+    return GP_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    int n = 0;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kBatchLds) != hipSuccess) {
+      (void)hipGetLastError();
+      return GP_EDEVICE;
+    }
+    g_noalloc_ptr[dev] = (unsigned char*)p;
+    g_noalloc_cus[dev] = n > 0 ? n : 256;
+  }
+  *ptr = g_noalloc_ptr[dev];
+  *cus = g_noalloc_cus[dev];
+  return GP_OK;
+}
+}  // namespace
+
+gp_status gp_partition_batch_noalloc(int32_t G, const int64_t* voff, const int64_t* eoff,
+                                     const int32_t* xadj, const int32_t* adjncy,
+                                     const int64_t* adjwgt, const int64_t* vwgt,
+                                     const gp_options* o, int32_t nmax, int32_t nnzmax,
+                                     int64_t ntot, int64_t nnztot, int8_t* part,
+                                     gp_result* res, void* stream) {
+  if (G < 0 || nmax < 0 || nnzmax < 0 || ntot < 0 || nnztot < 0 ||
+      (G > 0 && (!voff || !eoff || !xadj || !vwgt || !part || !res)) ||
+      (nnztot > 0 && (!adjncy || !adjwgt)))
+    return GP_EINVAL;
+  gp_status st = batch_options(o);
+  if (st != GP_OK) return st;
+  if (G == 0) return GP_OK;
+  unsigned char* base = nullptr;
+  int cus = 0;
+  if ((st = noalloc_setup(&base, &cus)) != GP_OK) return st;
+  // layout: queue head, arena offset, per-workgroup scratch, arena
+  uint64_t offs[32];
+  const uint64_t stride = wg_layout(nmax, nnzmax, offs);
+  // the levels of every graph stay in the arena until the launch ends and
+  // there is no rerun here, so the arena keeps twice the first estimate of
+  // gp_partition_batch when it can (fewer workgroups leave it more room)
+  const uint64_t arena_est =
+      (uint64_t)(3.0 * (double)(ntot * 57 + nnztot * 12)) + (uint64_t)G * 8192 + (1 << 20);
+  const uint64_t head_bytes = 512;
+  int nwg = 2 * cus < G ? 2 * cus : G;
+  while (nwg > 1 && head_bytes + (uint64_t)nwg * stride + 2 * arena_est > kNoAllocBytes) nwg--;
+  if (head_bytes + (uint64_t)nwg * stride + arena_est > kNoAllocBytes) return GP_ENOMEM;
+  BatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.G = G;
+  a.voff = voff;
+  a.eoff = eoff;
+  a.xadj = xadj;
+  a.adj = adjncy;
+  a.w = adjwgt;
+  a.vwgt = vwgt;
+  a.order = nullptr;  // input order
+  a.part = part;
+  a.res = res;
+  a.r0 = o->ratio[0];
+  a.r1 = o->ratio[1];
+  a.eps = o->eps_ppm;
+  a.bal = o->balance_on;
+  a.seed = o->seed;
+  a.C = o->coarsen_to;
+  a.R = o->match_rounds;
+  a.P = o->refine_passes;
+  a.K = o->init_trials;
+  a.head = (uint32_t*)base;
+  a.arena_off = (unsigned long long*)(base + 256);
+  a.wgs = base + head_bytes;
+  a.wgs_stride = stride;
+  a.arena = base + head_bytes + (uint64_t)nwg * stride;
+  a.arena_cap = kNoAllocBytes - head_bytes - (uint64_t)nwg * stride;
+  a.nmax = nmax;
+  a.nnzmax = nnzmax;
+  a.chunk = 1;
+  hipStream_t s = (hipStream_t)stream;
+  // the queue head and the arena offset start at zero: a fill kernel, no
+  // memset node, so that the two launches can be captured in a graph
+  k_batch_reset<<<1, 64, 0, s>>>(a.head, a.arena_off, a.ex);
+  k_batch<<<nwg, kBlock, kBatchLds, s>>>(a);
+  if (hipGetLastError() != hipSuccess) return GP_EDEVICE;
+  return GP_OK;
 }
 
 }  // extern "C"
