@@ -134,6 +134,35 @@ gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, in
 
 void gp_destroy(gp_graph* g);
 
+/* ---------------------------------------------------------------------
+ * k-way partition (CPU + GPU + further processors).  The paper leaves more
+ * than two processors to future work (Section VI) and gives each processor
+ * a share inversely proportional to its execution time (Eq. (1)
+ * generalised: R_i = (1/T_i) / sum_j (1/T_j)); here the shares come as
+ * integers ratio[0..k-1].  The partition is built by recursive bisection:
+ * the vertices of part range [lo, hi) (first [0, k)) are split with the
+ * two-way partition into [lo, mid) and [mid, hi), mid = lo + (hi - lo) / 2,
+ * at target ratio (sum of ratio[lo..mid), sum of ratio[mid..hi)) and the
+ * caller's eps and other options, on the subgraph they induce (vertices in
+ * ascending id order).  Each part's imbalance bound therefore compounds over
+ * the log2 k bisections above it.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  int64_t cut;           /* sum of w over edges whose ends lie in different parts */
+  int32_t feasible;      /* every bisection met its balance bound */
+  int32_t bisections;    /* two-way partitions run (ranges whose subgraph was not empty) */
+} gp_kway_result;
+
+/* k in [1, 1024]; ratio: host int64[k], each in [0, 2^40), sum in (0, 2^40);
+ * o: as for gp_partition (o->ratio is ignored, GP_LEARNED gives GP_EMODEL);
+ * part: caller-owned int32[n] receiving the part 0..k-1 of every vertex,
+ * device memory unless the handle was created with GP_HOST_PTRS; load: host
+ * int64[k] (may be NULL) receiving each part's weight in the balance column;
+ * res: host.  A range with a zero share receives no vertex unless its
+ * sibling's share is zero too. */
+gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const gp_options* o,
+                            int32_t* part, int64_t* load, gp_kway_result* res);
+
 /* Learned coarsest-level proposal (GP_LEARNED): a 3-layer message-passing
  * network, hidden size 64, whose 25,153 BF16 parameters (uint16 bits, host
  * memory) are laid out as Win[64][4], b_in[64], 3 x (Ws[64][64], Wn[64][64],

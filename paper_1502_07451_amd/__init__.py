@@ -52,6 +52,11 @@ class Result(ctypes.Structure):
                     levels=self.levels, used_learned=self.used_learned, status=self.status)
 
 
+class KwayResult(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("feasible", ctypes.c_int32),
+                ("bisections", ctypes.c_int32)]
+
+
 class ProfRow(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("executed", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -94,6 +99,9 @@ def _load():
     lib.gp_partition_batch.restype = ctypes.c_int
     lib.gp_batch_destroy.argtypes = [vp]
     lib.gp_batch_destroy.restype = None
+    lib.gp_partition_kway.argtypes = [vp, i32, vp, ctypes.POINTER(Options), vp, vp,
+                                      ctypes.POINTER(KwayResult)]
+    lib.gp_partition_kway.restype = ctypes.c_int
     lib.gp_partition_batch_noalloc.argtypes = [i32, vp, vp, vp, vp, vp, vp,
                                                ctypes.POINTER(Options), i32, i32, i64, i64, vp,
                                                vp, vp]
@@ -236,6 +244,27 @@ class Graph:
         if trace_cap > 0:
             return part, res, tr.reshape(trace_cap, 8)[:res.levels + 1].copy()
         return part, res
+
+    def partition_kway(self, k: int, ratio, opts: Options | None = None, part=None):
+        """gp_partition_kway: returns (part int32[n] with parts 0..k-1, KwayResult,
+        list of the k part loads)."""
+        import torch
+        opts = opts or options()
+        if part is None:
+            if self.host:
+                part = np.zeros(max(self.n, 1), np.int32)
+            else:
+                part = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        r = np.ascontiguousarray(ratio, dtype=np.int64)
+        if r.size != k:
+            raise ValueError(f"ratio needs {k} shares")
+        load = np.zeros(max(k, 1), np.int64)
+        res = KwayResult()
+        st = _lib.gp_partition_kway(self._h, int(k), _ptr(r), ctypes.byref(opts), _ptr(part),
+                                    _ptr(load), ctypes.byref(res))
+        if st != OK:
+            raise GPError(st, "gp_partition_kway")
+        return part[:self.n], res, [int(x) for x in load[:k]]
 
     def level(self, level: int) -> dict:
         """Level `level` of the last partition (host numpy arrays): n, xadj,

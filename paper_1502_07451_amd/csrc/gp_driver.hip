@@ -13,6 +13,8 @@
 #include <utility>
 #include <vector>
 
+constexpr int kKwayMax = 1024;
+
 #include "../../include/gp.h"
 #include "gp_launch.h"
 #include "gp_mpnn.h"
@@ -108,6 +110,10 @@ struct gp_graph {
   DBuf<float> m_inv, m_score;
   DBuf<int32_t> m_order;
   DBuf<int8_t> m_lp, m_save;  // refined learned proposal (coarsest), plain level-0 result
+  // k-way partition: labels, subgraph extraction and the subgraph's bisection
+  DBuf<int32_t> kw_label, kw_keep, kw_newid, kw_sxadj, kw_sadj;
+  DBuf<int64_t> kw_tiles, kw_tot, kw_sw, kw_svwgt, kw_acc;
+  DBuf<int8_t> kw_spart;
   Ctrl* ctrl = nullptr;
   Ctrl* hctrl = nullptr;  // pinned
   // profiling
@@ -170,6 +176,9 @@ struct gp_graph {
     i_adjc.release(); i_list.release();
     m_ha.release(); m_hb.release(); m_inv.release(); m_score.release(); m_order.release();
     m_lp.release(); m_save.release();
+    kw_label.release(); kw_keep.release(); kw_newid.release(); kw_sxadj.release();
+    kw_sadj.release(); kw_tiles.release(); kw_tot.release(); kw_sw.release(); kw_svwgt.release();
+    kw_acc.release(); kw_spart.release();
     if (ctrl) (void)hipFree(ctrl);
     if (hctrl) (void)hipHostFree(hctrl);
     for (int i = 0; i < prof.npool; i++)
@@ -718,6 +727,100 @@ gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, in
     HIPCHK(hipMemcpyAsync(match, l->match.p, 4 * nv, hipMemcpyDeviceToHost, s));
   if (part && nv) HIPCHK(hipMemcpyAsync(part, l->part.p, nv, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return GP_OK;
+}
+
+// k-way partition by recursive bisection of part ranges (see gp_kway.hip)
+gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const gp_options* o,
+                            int32_t* part, int64_t* load, gp_kway_result* res) {
+  if (!g || !ratio || !res || k < 1 || k > kKwayMax || (g->n > 0 && !part)) return GP_EINVAL;
+  const int64_t lim = (int64_t)1 << 40;
+  int64_t rsum = 0;
+  for (int i = 0; i < k; i++) {
+    if (ratio[i] < 0 || ratio[i] >= lim) return GP_EINVAL;
+    rsum += ratio[i];
+  }
+  if (rsum == 0 || rsum >= lim) return GP_EINVAL;
+  gp_options o2 = *o;
+  o2.ratio[0] = 1;
+  o2.ratio[1] = 1;
+  if (o2.flags & GP_LEARNED) return GP_EMODEL;
+  gp_status st = check_options(&o2);
+  if (st != GP_OK) return st;
+  const int32_t n = g->n;
+  gp_kway_result r;
+  memset(&r, 0, sizeof(r));
+  r.feasible = 1;
+  if (n == 0) {
+    if (load)
+      for (int i = 0; i < k; i++) load[i] = 0;
+    *res = r;
+    return GP_OK;
+  }
+  hipStream_t s = g->stream;
+  Level* l0 = g->lv[0];
+  const int ntiles = (n + 1023) / 1024;
+  if (!g->kw_label.ensure(n) || !g->kw_keep.ensure(n) || !g->kw_newid.ensure(n) ||
+      !g->kw_sxadj.ensure((size_t)n + 1) || !g->kw_sadj.ensure((size_t)g->nnz) ||
+      !g->kw_sw.ensure((size_t)g->nnz) || !g->kw_svwgt.ensure(2 * (size_t)n) ||
+      !g->kw_tiles.ensure(2 * (size_t)ntiles) || !g->kw_tot.ensure(2) ||
+      !g->kw_acc.ensure((size_t)k + 1) || !g->kw_spart.ensure(n))
+    return GP_ENOMEM;
+  int32_t* label = g->kw_label.p;
+  LCHK(launch_kw_zero(label, n, g->kw_acc.p, k + 1, s));
+  // ranges still to split, depth first; the subproblems are independent, so
+  // the order does not change the result
+  std::vector<std::pair<int32_t, int32_t>> todo{{0, k}};
+  while (!todo.empty()) {
+    const int32_t lo = todo.back().first, hi = todo.back().second;
+    todo.pop_back();
+    if (hi - lo < 2) continue;
+    const int32_t mid = lo + (hi - lo) / 2;
+    int64_t r0 = 0, r1 = 0;
+    for (int i = lo; i < mid; i++) r0 += ratio[i];
+    for (int i = mid; i < hi; i++) r1 += ratio[i];
+    LCHK(launch_kw_extract_a(n, l0->xadj.p, l0->adj.p, label, lo, g->kw_keep.p, g->kw_tiles.p,
+                             g->kw_tiles.p + ntiles, g->kw_tot.p, s));
+    int64_t tot[2];
+    HIPCHK(hipMemcpyAsync(tot, g->kw_tot.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (tot[0] == 0) continue;  // no vertex carries this range
+    LCHK(launch_kw_extract_b(n, l0->xadj.p, l0->adj.p, l0->w.p, l0->vc.p, l0->vg.p, label, lo,
+                             g->kw_keep.p, g->kw_tiles.p, g->kw_tiles.p + ntiles, g->kw_tot.p,
+                             g->kw_newid.p, g->kw_sxadj.p, g->kw_sadj.p, g->kw_sw.p,
+                             g->kw_svwgt.p, s));
+    if (r0 + r1 > 0) {
+      gp_graph* sub = nullptr;
+      st = gp_create(&sub, (int32_t)tot[0], g->kw_sxadj.p, g->kw_sadj.p, g->kw_sw.p,
+                     g->kw_svwgt.p, 0, s);
+      if (st != GP_OK) return st;
+      o2.ratio[0] = r0;
+      o2.ratio[1] = r1;
+      gp_result br;
+      st = run_partition(sub, &o2, g->kw_spart.p, &br, nullptr, 0);
+      gp_destroy(sub);
+      if (st != GP_OK) return st;
+      r.feasible &= br.feasible;
+      r.bisections++;
+      LCHK(launch_kw_apply(n, label, lo, mid, g->kw_newid.p, g->kw_spart.p, s));
+    }
+    todo.push_back({mid, hi});
+    todo.push_back({lo, mid});
+  }
+  const int64_t* b = o->balance_on ? l0->vg.p : l0->vc.p;
+  LCHK(launch_kw_stats(n, l0->xadj.p, l0->adj.p, l0->w.p, label, b, g->kw_acc.p,
+                       g->kw_acc.p + 1, s));
+  std::vector<int64_t> acc((size_t)k + 1);
+  HIPCHK(hipMemcpyAsync(acc.data(), g->kw_acc.p, sizeof(int64_t) * (k + 1),
+                        hipMemcpyDeviceToHost, s));
+  const hipMemcpyKind kout =
+      (g->flags & GP_HOST_PTRS) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HIPCHK(hipMemcpyAsync(part, label, sizeof(int32_t) * (size_t)n, kout, s));
+  HIPCHK(hipStreamSynchronize(s));
+  r.cut = acc[0] / 2;
+  if (load)
+    for (int i = 0; i < k; i++) load[i] = acc[1 + i];
+  *res = r;
   return GP_OK;
 }
 

@@ -112,4 +112,23 @@ bool launch_sort_rows(int32_t n, const int32_t* xadj, const int32_t* adj, const 
                       int32_t* oadj, int64_t* ow, Ctrl* ctrl, hipStream_t s);
 bool launch_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_t* vg, hipStream_t s);
 
+// ---- k-way partition by recursive bisection (gp_kway.hip)
+bool launch_kw_zero(int32_t* label, int32_t n, int64_t* acc, int nacc, hipStream_t s);
+// subgraph of the vertices labelled lo: per-tile member and entry counts and
+// their scans; tot[0..1] = vertices and entries of the subgraph
+bool launch_kw_extract_a(int32_t n, const int32_t* xadj, const int32_t* adj, const int32_t* label,
+                         int32_t lo, int32_t* keep, int64_t* tile_m, int64_t* tile_e,
+                         int64_t* tot, hipStream_t s);
+// its ids, CSR (rows in order, neighbour ids renumbered) and vertex weights
+bool launch_kw_extract_b(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                         const int64_t* vc, const int64_t* vg, const int32_t* label, int32_t lo,
+                         const int32_t* keep, const int64_t* tile_m, const int64_t* tile_e,
+                         const int64_t* tot, int32_t* newid, int32_t* sxadj, int32_t* sadj,
+                         int64_t* sw, int64_t* svwgt, hipStream_t s);
+bool launch_kw_apply(int32_t n, int32_t* label, int32_t lo, int32_t mid, const int32_t* newid,
+                     const int8_t* spart, hipStream_t s);
+bool launch_kw_stats(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                     const int32_t* label, const int64_t* b, int64_t* ext_sum, int64_t* load,
+                     hipStream_t s);
+
 }  // namespace gpk
