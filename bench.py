@@ -406,15 +406,15 @@ def main():
             del refs
         del graphs_b
 
-    # learned coarsest-level proposal vs the plain bisection on both of its
-    # evaluation DAGs: the 1M-vertex layered DAG (1:3, 5 %) and Cholesky T=64
+    # learned coarsest-level proposal vs the plain bisection on its evaluation
+    # DAGs: the 1M-vertex layered DAG (1:3, 5 %), Cholesky T=64 and LU T=48
     # (1:4, 3 %)
     wpath = os.path.join(ROOT, "paper_1502_07451_amd", "mpnn_weights.bin")
     if not args.no_extra and os.path.exists(wpath):
         from paper_1502_07451_amd import learn
         w = learn.load_weights(wpath)
         out["learned"] = (learn.gain_test(w, [dagen.config_layered1m()], L4M_OPTS, dev, reps=3)
-                          + learn.gain_test(w, graphs2[:1], STEP2_OPTS, dev, reps=3))
+                          + learn.gain_test(w, graphs2, STEP2_OPTS, dev, reps=3))
     print(json.dumps(out), flush=True)
 
 

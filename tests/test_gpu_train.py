@@ -94,10 +94,9 @@ def test_gradients_vs_fp64(gp, seed):
         a, b = grad[o:o + k].astype(np.float64), ref[o:o + k]
         o += k
         nb = np.linalg.norm(b)
-        if nb < 1e-3 * np.linalg.norm(ref):
-            continue  # a tensor with next to no gradient: covered by the total
         rel = np.linalg.norm(a - b) / nb
-        assert rel <= 3e-2, f"{name}: relative error {rel:.4g}"
+        say(f"  {name}: relative error {rel:.4g}")
+        assert rel <= 2e-2, f"{name}: relative error {rel:.4g}"
 
 
 def test_adam_lowers_loss(gp):
