@@ -415,6 +415,28 @@ def main():
         w = learn.load_weights(wpath)
         out["learned"] = (learn.gain_test(w, [dagen.config_layered1m()], L4M_OPTS, dev, reps=3)
                           + learn.gain_test(w, graphs2, STEP2_OPTS, dev, reps=3))
+    # schedule simulation (the paper's runtime comparison): eager, dmda-like
+    # and the partition on 3 CPU workers + 1 GPU worker, tiled Cholesky T=16
+    # (b = 512, 2 MiB tiles), time unit = one flop at CPU speed, the link
+    # moving one byte per unit; GPU speed 4x (small gap) and 50x (large gap)
+    if not args.no_extra:
+        import numpy as np
+        sched = []
+        for rate in (4, 50):
+            g = dagen.cholesky(16, 512, rate=rate)
+            tc, tg = int(g.vwgt[:, 0].sum()) // 3, int(g.vwgt[:, 1].sum())
+            _, (r0, r1) = gp.ratio_from_times(tc, tg)
+            hg = gp.Graph(g.n, g.xadj, g.adjncy, g.adjwgt, np.ascontiguousarray(g.vwgt))
+            part, pres = hg.partition(gp.options(ratio=(r0, r1), eps_ppm=30000))
+            hg.close()
+            row = {"dag": "cholesky_T16", "gpu_speedup": rate, "ratio": [r0, r1],
+                   "gp_cut": pres.cut}
+            for name, pol in (("eager", gp.SIM_EAGER), ("dmda", gp.SIM_DMDA), ("gp", gp.SIM_GP)):
+                res, _, _ = gp.simulate(g, pol, part=part, ncpu=3, ngpu=1, latency=0, bw=1)
+                row[name] = {"makespan": res.makespan, "transfers": res.transfers,
+                             "bytes": res.bytes, "tasks_cpu_gpu": [res.tasks[0], res.tasks[1]]}
+            sched.append(row)
+        out["schedule"] = sched
     print(json.dumps(out), flush=True)
 
 

@@ -297,6 +297,33 @@ gp_status gp_train_grad(gp_trainer* t, int32_t g0, int32_t g1, float* grad, floa
 gp_status gp_train_params(gp_trainer* t, float* f32, uint16_t* bf16);
 void gp_train_destroy(gp_trainer* t);
 
+/* ---------------------------------------------------------------------
+ * Schedule simulator (host code): replays a task DAG on ncpu CPU workers
+ * (memory node 0) and ngpu GPU workers (node 1) under one of the runtime
+ * policies the paper compares (Section IV-C): eager (the worker free first),
+ * dmda-like (the worker where the task would finish first, transfers
+ * included) or gp (the node part[v] names, e.g. a gp_partition result).
+ * Tasks are placed in id order, which must be a topological order (every
+ * dependency u-v points from the smaller id to the larger).  vwgt[v] =
+ * (cpu cost, gpu cost) in time units; a dependency between nodes costs one
+ * transfer of its edge's bytes over a single link (latency + ceil(bytes /
+ * bw) time units, transfers in request order), made once per producer and
+ * destination node.  All pointers are host memory; task_node (int8[n]) and
+ * task_finish (int64[n]) may be NULL.
+ * --------------------------------------------------------------------- */
+enum { GP_SIM_EAGER = 0, GP_SIM_DMDA = 1, GP_SIM_GP = 2 };
+typedef struct {
+  int64_t makespan;      /* finish time of the last task */
+  int64_t transfers;     /* transfers between the memory nodes */
+  int64_t bytes;         /* bytes they moved */
+  int64_t busy[2];       /* summed task time on the CPU workers, on the GPU workers */
+  int64_t tasks[2];      /* tasks placed on the CPU, on the GPU */
+} gp_sim_result;
+gp_status gp_simulate(int32_t n, const int32_t* xadj, const int32_t* adjncy,
+                      const int64_t* adjwgt, const int64_t* vwgt, const int8_t* part,
+                      int32_t policy, int32_t ncpu, int32_t ngpu, int64_t latency, int64_t bw,
+                      gp_sim_result* res, int8_t* task_node, int64_t* task_finish);
+
 const char* gp_strerror(gp_status s);
 
 #ifdef __cplusplus

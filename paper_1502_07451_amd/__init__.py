@@ -57,6 +57,36 @@ class KwayResult(ctypes.Structure):
                 ("bisections", ctypes.c_int32)]
 
 
+class SimResult(ctypes.Structure):
+    _fields_ = [("makespan", ctypes.c_int64), ("transfers", ctypes.c_int64),
+                ("bytes", ctypes.c_int64), ("busy", ctypes.c_int64 * 2),
+                ("tasks", ctypes.c_int64 * 2)]
+
+
+SIM_EAGER, SIM_DMDA, SIM_GP = 0, 1, 2
+
+
+def simulate(g, policy: int, part=None, ncpu: int = 3, ngpu: int = 1, latency: int = 0,
+             bw: int = 1):
+    """gp_simulate on host arrays of a graph (dagen.Graph-like).  Returns
+    (SimResult, task node int8[n], task finish int64[n])."""
+    n = int(g.n)
+    xadj = np.ascontiguousarray(g.xadj, np.int32)
+    adj = np.ascontiguousarray(g.adjncy if len(g.adjncy) else np.zeros(1), np.int32)
+    w = np.ascontiguousarray(g.adjwgt if len(g.adjwgt) else np.zeros(1), np.int64)
+    vw = np.ascontiguousarray(g.vwgt, np.int64).reshape(-1)
+    pt = None if part is None else np.ascontiguousarray(part, np.int8)
+    node = np.zeros(max(n, 1), np.int8)
+    fin = np.zeros(max(n, 1), np.int64)
+    res = SimResult()
+    st = _lib.gp_simulate(n, _ptr(xadj), _ptr(adj), _ptr(w), _ptr(vw), _ptr(pt), int(policy),
+                          int(ncpu), int(ngpu), int(latency), int(bw), ctypes.byref(res),
+                          _ptr(node), _ptr(fin))
+    if st != OK:
+        raise GPError(st, "gp_simulate")
+    return res, node[:n], fin[:n]
+
+
 class ProfRow(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("executed", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -101,6 +131,9 @@ def _load():
     lib.gp_batch_destroy.restype = None
     lib.gp_partition_kway.argtypes = [vp, i32, vp, ctypes.POINTER(Options), vp, vp,
                                       ctypes.POINTER(KwayResult)]
+    lib.gp_simulate.argtypes = [i32, vp, vp, vp, vp, vp, i32, i32, i32, i64, i64,
+                                ctypes.POINTER(SimResult), vp, vp]
+    lib.gp_simulate.restype = ctypes.c_int
     lib.gp_partition_kway.restype = ctypes.c_int
     lib.gp_partition_batch_noalloc.argtypes = [i32, vp, vp, vp, vp, vp, vp,
                                                ctypes.POINTER(Options), i32, i32, i64, i64, vp,
