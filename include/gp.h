@@ -58,8 +58,19 @@ typedef enum {
 enum {
   GP_HOST_PTRS = 1,  /* input / output pointers are host memory (else device memory) */
   GP_LEARNED = 2,    /* run the learned coarsest-level proposal beside the plain one */
-  GP_TRACE = 4       /* record per-level statistics (costs one extra pass per level) */
+  GP_TRACE = 4,      /* record per-level statistics (costs one extra pass per level) */
+  GP_TIME_BALANCE = 8 /* balance each side in its own cost column (below) */
 };
+/* GP_TIME_BALANCE lifts the assumption that every kernel has the same
+ * CPU/GPU performance ratio (Section IV-D): side 0 is measured by its CPU
+ * cost and side 1 by its GPU cost, each against its own bound tgt_p =
+ * floor(W_p r_p / R), maxw_p = ceil(W_p r_p (10^6 + eps) / (R 10^6)) with W_0
+ * the CPU-cost total and W_1 the GPU-cost total (ratio = {W_1, W_0}, Eq. (1)
+ * on the totals, makes both bounds the same time).  Coarsening and the
+ * initial bisection use the balance column as usual; the coarsest bisection
+ * is then refined under the two bounds, and so is every level on the way
+ * up.  res->load holds the two times; feasible refers to these bounds.
+ * Not with GP_LEARNED, the batched calls or gp_partition_kway (GP_EINVAL). */
 
 typedef struct {
   int64_t ratio[2];      /* CPU : GPU target shares, Eq. (1)-(2); each in [0, 2^40), sum > 0 */

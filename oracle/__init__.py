@@ -19,6 +19,7 @@ _lib = None
 
 OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)
 FLAG_LEARNED = 2
+FLAG_TIME = 8
 
 
 def build(extra_flags=()) -> str:

@@ -390,7 +390,10 @@ int64_t or_cut(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t
   return s / 2;
 }
 
-typedef struct { int32_t v; int64_t gain; int64_t b; } Cand;
+/* b: weight the candidate adds to the destination side; bs: weight it takes
+   from its own side (the same column unless the two sides are measured in
+   different columns) */
+typedef struct { int32_t v; int64_t gain; int64_t b; int64_t bs; } Cand;
 
 /* candidates in admission order: larger gain first, then smaller id */
 static int cand_cmp(const void* a, const void* b) {
@@ -416,8 +419,12 @@ static int cand_cmp(const void* a, const void* b) {
 /*  consecutive improvement passes that move nothing, or after P passes.     */
 /* Returns the passes run; *moves_out gets the number of vertices moved.     */
 /* ------------------------------------------------------------------------ */
-static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
-                     const int64_t* maxw, int P, int64_t* moves_out) {
+/* b[p]: the weight column that measures side p (the same array for both
+   sides, except in time balance, where side 0 counts CPU cost and side 1 GPU
+   cost); a vertex moving from s to d takes b[s][v] from s and adds b[d][v]
+   to d. */
+static int refine_og2(const OG* g, const int64_t* const b[2], int8_t* part, int64_t* pw,
+                      const int64_t* maxw, int P, int64_t* moves_out) {
   int32_t n = g->n;
   int64_t* gain = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   Cand* list = (Cand*)malloc(sizeof(Cand) * (size_t)(n > 0 ? n : 1));
@@ -432,19 +439,24 @@ static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
       int s = over, d = 1 - s;
       int32_t k = 0;
       for (int32_t v = 0; v < n; v++)
-        if (part[v] == s) { list[k].v = v; list[k].gain = gain[v]; list[k].b = b[v]; k++; }
+        if (part[v] == s) {
+          list[k].v = v; list[k].gain = gain[v]; list[k].b = b[d][v]; list[k].bs = b[s][v];
+          k++;
+        }
       qsort(list, (size_t)k, sizeof(Cand), cand_cmp);
       int64_t excess = pw[s] - maxw[s], budget = maxw[d] - pw[d];
+      /* the shortest prefix that takes the excess off s, cut back to the
+         longest prefix that d can absorb */
       int32_t k1 = 0;
       int64_t acc = 0;
-      while (k1 < k && acc < excess) { acc += list[k1].b; k1++; }
+      while (k1 < k && acc < excess) { acc += list[k1].bs; k1++; }
       int32_t k2 = 0;
       acc = 0;
       while (k2 < k && acc + list[k2].b <= budget) { acc += list[k2].b; k2++; }
       int32_t take = k1 < k2 ? k1 : k2;
       for (int32_t j = 0; j < take; j++) {
         part[list[j].v] = (int8_t)d;
-        pw[s] -= list[j].b;
+        pw[s] -= list[j].bs;
         pw[d] += list[j].b;
       }
       moves += take;
@@ -454,7 +466,8 @@ static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
       int32_t k = 0;
       for (int32_t v = 0; v < n; v++)
         if (part[v] == s && gain[v] > 0) {
-          list[k].v = v; list[k].gain = gain[v]; list[k].b = b[v]; k++;
+          list[k].v = v; list[k].gain = gain[v]; list[k].b = b[d][v]; list[k].bs = b[s][v];
+          k++;
         }
       qsort(list, (size_t)k, sizeof(Cand), cand_cmp);
       int64_t budget = maxw[d] - pw[d];
@@ -463,7 +476,7 @@ static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
       while (take < k && acc + list[take].b <= budget) { acc += list[take].b; take++; }
       for (int32_t j = 0; j < take; j++) {
         part[list[j].v] = (int8_t)d;
-        pw[s] -= list[j].b;
+        pw[s] -= list[j].bs;
         pw[d] += list[j].b;
       }
       moves += take;
@@ -475,6 +488,12 @@ static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
   free(list);
   if (moves_out) *moves_out = moves;
   return passes;
+}
+
+static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
+                     const int64_t* maxw, int P, int64_t* moves_out) {
+  const int64_t* const bb[2] = {b, b};
+  return refine_og2(g, bb, part, pw, maxw, P, moves_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -642,9 +661,9 @@ int or_init_bisect(int32_t n, const int32_t* xadj, const int32_t* adj, const int
    coarsest level's bisection on entry (pw its part weights) and the level-0
    bisection on return.  Writes the coarsest level's and every finer level's
    trace row. */
-static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, const int64_t* pairs,
-                     const int64_t* maxw, int P, int8_t** partp, int64_t* pw, int64_t* trace,
-                     int32_t trace_cap) {
+static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, int time_mode,
+                     const int64_t* pairs, const int64_t* maxw, int P, int8_t** partp,
+                     int64_t* pw, int64_t* trace, int32_t trace_cap) {
   int8_t* part = *partp;
   if (trace && L < trace_cap) {
     OG* g = &lv[L];
@@ -662,7 +681,9 @@ static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, const int64_t
     free(part);
     part = next;
     int64_t moves = 0;
-    int passes = refine_og(g, b, part, pw, maxw, P, &moves);
+    const int64_t* const bt[2] = {g->vc, g->vg};
+    int passes = time_mode ? refine_og2(g, bt, part, pw, maxw, P, &moves)
+                           : refine_og(g, b, part, pw, maxw, P, &moves);
     if (passes < 0) { *partp = part; return OR_ENOMEM; }
     if (trace && l < trace_cap) {
       int64_t* t = trace + 8 * l;
@@ -676,6 +697,16 @@ static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, const int64_t
 }
 
 #define OR_FLAG_LEARNED 2
+/* Time balance (a reading of the paper's remark that the method assumes one
+   CPU/GPU performance ratio for all kernels, Section IV-D): part 0 is
+   measured by its CPU cost and part 1 by its GPU cost, each against its own
+   bound tgt_p = floor(W_p r_p / R), maxw_p = ceil(W_p r_p (10^6 + eps) /
+   (R 10^6)) with W_0 the CPU-cost total and W_1 the GPU-cost total (with
+   r = (W_1, W_0), Eq. (1) on the totals, both bounds are the same time).
+   The coarsening and the initial bisection use the balance column as
+   usual; from the coarsest level on, the refinement works with the two
+   columns, its rebalance passes bringing each side under its own bound. */
+#define OR_FLAG_TIME 8
 
 int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
                  const int64_t* vwgt, const int64_t* opts, const void* model, int8_t* part_out,
@@ -689,6 +720,8 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
   if (eps < 0 || eps > 1000000 || (bal != 0 && bal != 1)) return OR_EINVAL;
   if (C < 1 || R < 0 || R > 64 || P < 0 || P > 64 || K < 1 || K > 64) return OR_EINVAL;
   if ((flags & OR_FLAG_LEARNED) && !model) return OR_EMODEL;
+  if ((flags & OR_FLAG_LEARNED) && (flags & OR_FLAG_TIME)) return OR_EINVAL;
+  const int time_mode = (flags & OR_FLAG_TIME) != 0;
   if (n < 0) return OR_EINVAL;
 
   OG lv[OR_MAX_LEVELS + 1];
@@ -753,10 +786,30 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
       }
     }
   }
-  if (rc == OR_OK) rc = uncoarsen(lv, cmap, L, (int)bal, pairs, maxw, (int)P, &part, pw, trace,
-                                  trace_cap);
+  if (rc == OR_OK && time_mode) {
+    /* each side in its own column from here on */
+    int64_t Wt[2] = {0, 0}, tt[2], mt[2];
+    for (int32_t v = 0; v < n; v++) { Wt[0] += lv[0].vc[v]; Wt[1] += lv[0].vg[v]; }
+    or_balance(Wt[0], r0, r1, (int32_t)eps, tt, mt);
+    maxw[0] = mt[0];
+    tgt[0] = tt[0];
+    or_balance(Wt[1], r0, r1, (int32_t)eps, tt, mt);
+    maxw[1] = mt[1];
+    tgt[1] = tt[1];
+    OG* g = &lv[L];
+    pw[0] = pw[1] = 0;
+    for (int32_t v = 0; v < g->n; v++) {
+      if (part[v] == 0) pw[0] += g->vc[v];
+      else pw[1] += g->vg[v];
+    }
+    /* the coarsest bisection is refined once more under the two bounds */
+    const int64_t* const bt[2] = {g->vc, g->vg};
+    if (refine_og2(g, bt, part, pw, maxw, (int)P, NULL) < 0) rc = OR_ENOMEM;
+  }
+  if (rc == OR_OK) rc = uncoarsen(lv, cmap, L, (int)bal, time_mode, pairs, maxw, (int)P, &part,
+                                  pw, trace, trace_cap);
   if (rc == OR_OK && lp) {
-    rc = uncoarsen(lv, cmap, L, (int)bal, pairs, maxw, (int)P, &lp, lpw, ltrace, trace_cap);
+    rc = uncoarsen(lv, cmap, L, (int)bal, 0, pairs, maxw, (int)P, &lp, lpw, ltrace, trace_cap);
     if (rc == OR_OK) {
       /* the plain bisection judges the learned one on the input graph: the
          learned result is kept only when it is strictly better in

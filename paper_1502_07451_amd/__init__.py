@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgp.so")
 
 OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)
-HOST_PTRS, LEARNED, TRACE = 1, 2, 4
+HOST_PTRS, LEARNED, TRACE, TIME_BALANCE = 1, 2, 4, 8
 
 
 class GPError(RuntimeError):

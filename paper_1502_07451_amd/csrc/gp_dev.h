@@ -292,6 +292,18 @@ struct ListItems {
   }
 };
 
+// the same candidates weighted by what they take from their side
+template <class Items>
+struct SrcItems {
+  Items it;
+  __device__ __forceinline__ uint32_t count() const { return it.count(); }
+  __device__ __forceinline__ bool get(uint32_t i, Cand& c) const {
+    if (!it.get(i, c)) return false;
+    c.b = c.bs;
+    return true;
+  }
+};
+
 struct LdsItems {
   const int64_t* gain;
   const int64_t* b;
@@ -305,6 +317,7 @@ struct LdsItems {
     if (mode == 0 && g <= 0) return false;
     c.gain = g;
     c.b = b[i];
+    c.bs = c.b;
     c.v = (int32_t)i;
     c.pad = 0;
     return true;

@@ -284,6 +284,7 @@ static gp_status check_options(const gp_options* o) {
   if (o->flags & GP_LEARNED) {
     const MpModel* m = (const MpModel*)o->model;
     if (!m || m->magic != kMpMagic) return GP_EMODEL;
+    if (o->flags & GP_TIME_BALANCE) return GP_EINVAL;
   }
   return GP_OK;
 }
@@ -572,6 +573,29 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
                        g->m_lp.p, g->ctrl->lpw, s));
     }
   }
+  // Time balance: from here on, side 0 is measured by its CPU cost and side
+  // 1 by its GPU cost, each against its own bound; the coarsest bisection is
+  // refined once more under the two bounds before the uncoarsening
+  const bool time_mode = (o->flags & GP_TIME_BALANCE) != 0;
+  const int rbal = time_mode ? 0 : bal;  // the refinement's side-0 column
+  if (time_mode) {
+    int64_t tt[2], mt[2];
+    host_balance(g->sum[0], o->ratio, o->eps_ppm, tt, mt);
+    maxw[0] = mt[0];
+    host_balance(g->sum[1], o->ratio, o->eps_ppm, tt, mt);
+    maxw[1] = mt[1];
+    LCHK(launch_final_stats(cl->view(bal), cl->vc.p, cl->vg.p, cl->part.p, g->ctrl,
+                            team_width_for(cl->n, cl->nnz), sc.partials, s));
+    LCHK(launch_time_bounds(g->ctrl, maxw[0], maxw[1], P, s));
+    if (cl->n > 0) {
+      HIPCHK(hipMemsetAsync(g->r_mark.p, 0, sizeof(int32_t) * cl->n, s));
+      const RefArrays ra{g->r_ext.p, g->r_inn.p, g->r_mark.p, cl->vg.p};
+      const int tw = team_width_for(cl->n, cl->nnz);
+      for (int p = 0; p < P; p++)
+        LCHK(launch_refine_pass(cl->view(0), cl->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
+                                &g->ctrl->lvl_pass[L], p, P, ra, s));
+    }
+  }
   // per-level statistics of the current bisection of level l (GP_TRACE)
   auto record = [&](int l, bool coarsest, int64_t* tr) -> gp_status {
     if (!tr || l >= trace_cap) return GP_OK;
@@ -586,8 +610,8 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     t[2] = coarsest ? 0 : h.ref.pass;
     t[3] = coarsest ? 0 : h.ref.total_moves;
     t[4] = h.res_ext / 2;
-    t[5] = h.res_load[0];
-    t[6] = h.res_load[1];
+    t[5] = time_mode ? h.res_time[0] : h.res_load[0];
+    t[6] = time_mode ? h.res_time[1] : h.res_load[1];
     t[7] = pairs[l];
     return GP_OK;
   };
@@ -601,10 +625,10 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
       Level* c = g->lv[l + 1];
       g->prof.level = l;
       g->prof.idx = 0;
-      const RefArrays ra{g->r_ext.p, g->r_inn.p, g->r_mark.p};
+      const RefArrays ra{g->r_ext.p, g->r_inn.p, g->r_mark.p, time_mode ? f->vg.p : nullptr};
       LCHK(launch_project(f->n, f->cmap.p, c->part.p, f->part.p, &g->ctrl->ref, P, ra.mark, s));
       const int tw = team_width_for(f->n, f->nnz);
-      const LevelView fv = f->view(bal);
+      const LevelView fv = f->view(rbal);
       for (int p = 0; p < P; p++) {
         g->prof.idx = p;
         LCHK(launch_refine_pass(fv, f->part.p, &g->ctrl->ref, sc.list, sc.partials, tw,
@@ -652,8 +676,8 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   HIPCHK(hipMemcpyAsync(part, l0->part.p, (size_t)n, kout, s));
   HIPCHK(hipStreamSynchronize(s));
   r.cut = h.res_ext / 2;
-  r.load[0] = h.res_load[0];
-  r.load[1] = h.res_load[1];
+  r.load[0] = time_mode ? h.res_time[0] : h.res_load[0];
+  r.load[1] = time_mode ? h.res_time[1] : h.res_load[1];
   r.time[0] = h.res_time[0];
   r.time[1] = h.res_time[1];
   r.feasible = (r.load[0] <= maxw[0] && r.load[1] <= maxw[1]) ? 1 : 0;
@@ -745,6 +769,7 @@ gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const 
   o2.ratio[0] = 1;
   o2.ratio[1] = 1;
   if (o2.flags & GP_LEARNED) return GP_EMODEL;
+  if (o2.flags & GP_TIME_BALANCE) return GP_EINVAL;
   gp_status st = check_options(&o2);
   if (st != GP_OK) return st;
   const int32_t n = g->n;

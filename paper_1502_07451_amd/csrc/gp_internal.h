@@ -26,9 +26,13 @@ constexpr int kMaxRounds = 64;
 constexpr int kInitBlock = 64;    // one wave per greedy-growing trial
 
 // candidate of a refinement pass: admission order is gain desc, id asc
+// b: weight the move adds to the destination side; bs: weight it takes from
+// the source side (equal unless the two sides are measured in different
+// columns: time balance)
 struct Cand {
   int64_t gain;
   int64_t b;
+  int64_t bs;
   int32_t v;
   int32_t pad;
 };
@@ -50,7 +54,7 @@ struct RefCtl {
   int64_t gmin_acc, gmax_acc;
   uint32_t ncand;
   uint32_t pad0;
-  int64_t moved_b, moved_n;
+  int64_t moved_b, moved_n, moved_bs;
   // totals
   int64_t total_moves;
   int64_t last_cut;

@@ -161,17 +161,19 @@ template <int TW>
 __global__ __launch_bounds__(kBlock) void k_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list,
                                                         int64_t* partials, int64_t* sext,
-                                                        int64_t* sinn) {
+                                                        int64_t* sinn, const int64_t* b1) {
   __shared__ SelShared sel;
   b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x, false,
-                    sext, sinn);
+                    sext, sinn, b1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_scan(int32_t n, const int8_t* part,
-                                                        const int64_t* b, const int64_t* sext,
-                                                        const int64_t* sinn, RefCtl* rc,
-                                                        Cand* list, int64_t* partials) {
-  b_refine_scan(n, part, b, sext, sinn, rc, list, partials, (int)blockIdx.x, (int)gridDim.x);
+                                                        const int64_t* b, const int64_t* b1,
+                                                        const int64_t* sext, const int64_t* sinn,
+                                                        RefCtl* rc, Cand* list,
+                                                        int64_t* partials) {
+  b_refine_scan(n, part, b, b1, sext, sinn, rc, list, partials, (int)blockIdx.x,
+                (int)gridDim.x);
 }
 
 template <int TW>
@@ -208,6 +210,19 @@ __global__ __launch_bounds__(kBlock) void k_project(int32_t n, const int32_t* cm
                                                     const int8_t* cpart, int8_t* part, RefCtl* rc,
                                                     int npass, int32_t* mark) {
   b_project(n, cmap, cpart, part, rc, npass, (int)blockIdx.x, (int)gridDim.x, mark);
+}
+
+// time balance: the loads become (CPU cost of side 0, GPU cost of side 1),
+// taken from the statistics kernel, with their own bounds; a new pass sequence
+__global__ void k_time_bounds(Ctrl* ctrl, int64_t maxw0, int64_t maxw1, int npass) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    RefCtl* rc = &ctrl->ref;
+    rc->pw[0] = ctrl->res_time[0];
+    rc->pw[1] = ctrl->res_time[1];
+    rc->maxw[0] = maxw0;
+    rc->maxw[1] = maxw1;
+    start_level(rc, npass);
+  }
 }
 
 __global__ void k_start_level(RefCtl* rc, int npass) {
@@ -536,7 +551,7 @@ static bool gain_tw(const LevelView& lv, const int8_t* part, RefCtl* rc, Cand* l
   // one row per team: the row loads of all vertices are in flight at once
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
   ProfScope ps(PK_REFINE_GAIN, TW, 4.0 * (lv.n + 1) + 12.0 * lv.nnz + 17.0 * lv.n, s);
-  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials, ra.ext, ra.inn);
+  k_refine_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, rc, list, partials, ra.ext, ra.inn, ra.b1);
   KCHECK();
   *grid_out = grid;
   return true;
@@ -572,7 +587,8 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
   } else {
     grid = grid_for(lv.n, kBlock);
     ProfScope ps(PK_REFINE_SCAN, 0, 25.0 * lv.n, s);
-    k_refine_scan<<<grid, kBlock, 0, s>>>(lv.n, part, lv.b, ra.ext, ra.inn, rc, list, partials);
+    k_refine_scan<<<grid, kBlock, 0, s>>>(lv.n, part, lv.b, ra.b1, ra.ext, ra.inn, rc, list,
+                                          partials);
     KCHECK();
   }
   if (lv.n <= kSettleMax) {
@@ -607,6 +623,12 @@ bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t*
                     int npass, int32_t* mark, hipStream_t s) {
   ProfScope ps(PK_PROJECT, 0, 10.0 * n, s);
   k_project<<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, cmap, cpart, part, rc, npass, mark);
+  KCHECK();
+  return true;
+}
+
+bool launch_time_bounds(Ctrl* ctrl, int64_t maxw0, int64_t maxw1, int npass, hipStream_t s) {
+  k_time_bounds<<<1, 64, 0, s>>>(ctrl, maxw0, maxw1, npass);
   KCHECK();
   return true;
 }

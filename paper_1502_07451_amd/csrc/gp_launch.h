@@ -88,6 +88,7 @@ struct RefArrays {
   int64_t* ext;   // n: weight to the other side, kept up to date across passes
   int64_t* inn;   // n: weight to the own side
   int32_t* mark;  // n: p + 1 for the vertices moved by pass p, cleared by the projection
+  const int64_t* b1;  // side 1's weight column when the sides use different ones, else null
 };
 
 // Pass p (of npass) of a level: the first pass computes every vertex's
@@ -100,6 +101,8 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
                     int npass, int32_t* mark, hipStream_t s);
 bool launch_start_level(RefCtl* rc, int npass, hipStream_t s);
+// time balance: loads from the last statistics launch, bounds (maxw0, maxw1)
+bool launch_time_bounds(Ctrl* ctrl, int64_t maxw0, int64_t maxw1, int npass, hipStream_t s);
 // partials: 5 int64 per block (grids are capped at 4096)
 bool launch_final_stats(const LevelView& lv, const int64_t* vc, const int64_t* vg,
                         const int8_t* part, Ctrl* ctrl, int tw, int64_t* partials,

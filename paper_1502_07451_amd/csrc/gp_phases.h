@@ -1010,6 +1010,7 @@ __device__ __forceinline__ void clear_pass_acc(RefCtl* rc) {
   rc->ncand = 0;
   rc->moved_b = 0;
   rc->moved_n = 0;
+  rc->moved_bs = 0;
 }
 
 // Called by every thread of one block once the pass totals are known.
@@ -1032,7 +1033,9 @@ __device__ void decide_admission(RefCtl* rc, const Items& items, uint32_t ncand,
       thr = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh, ncand);
     } else {
       const int64_t excess = rc->pw[s] - rc->maxw[s];
-      u128 t1 = select_prefix<BS>(items, gmin, idbits, tbits, 1, excess, sh, ncand);
+      // the covering prefix counts what the candidates take off side s
+      const SrcItems<Items> src{items};
+      u128 t1 = select_prefix<BS>(src, gmin, idbits, tbits, 1, excess, sh, ncand);
       u128 t2 = 0;
       if (cand_b > budget) t2 = select_prefix<BS>(items, gmin, idbits, tbits, 0, budget, sh, ncand);
       thr = t1 > t2 ? t1 : t2;
@@ -1055,12 +1058,14 @@ __device__ __forceinline__ bool admitted(const RefCtl& r, const Cand& c) {
   return cand_key(c, r.gmin, r.idbits) >= thr;
 }
 
-__device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_b, int64_t moved_n) {
+// moved_bs: weight the pass took off side s, moved_b: weight it added to d
+__device__ __forceinline__ void finish_pass(RefCtl* rc, int64_t moved_bs, int64_t moved_b,
+                                            int64_t moved_n) {
   const int s = rc->s, d = 1 - s;
   rc->last_ncand = rc->ncand;
   rc->last_d = d;
   rc->last_moved_n = moved_n;
-  rc->pw[s] -= moved_b;
+  rc->pw[s] -= moved_bs;
   rc->pw[d] += moved_b;
   rc->total_moves += moved_n;
   rc->last_cut = rc->ext_sum / 2;
@@ -1082,7 +1087,8 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
                                                         int64_t* partials, int bid_, int nblk_,
                                                         bool inline_tail = true,
                                                         int64_t* sext = nullptr,
-                                                        int64_t* sinn = nullptr) {
+                                                        int64_t* sinn = nullptr,
+                                                        const int64_t* b1 = nullptr) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   int mode, s;
@@ -1140,8 +1146,11 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
         }
         cand = pv == s && (mode == 1 || gain > 0);
         if (cand) {
+          // side 1 is measured in column b1 when one is given (time balance)
+          const int64_t w0 = lv.b[v], w1 = b1 ? b1[v] : w0;
           c.gain = gain;
-          c.b = lv.b[v];
+          c.b = s ? w0 : w1;
+          c.bs = s ? w1 : w0;
           c.v = v;
           cb += c.b;
           gmn = gain < gmn ? gain : gmn;
@@ -1239,7 +1248,7 @@ __device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl*
   __syncthreads();
   const RefCtl r = *rc;
   const int d = 1 - r.s;
-  int64_t mb = 0, mn = 0;
+  int64_t mb = 0, mbs = 0, mn = 0;
   if (r.admit != kAdmitNone) {
     const int64_t nc = r.ncand;
     constexpr int U = 4;  // candidate loads in flight per thread
@@ -1257,15 +1266,17 @@ __device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl*
           part[c[u].v] = (int8_t)d;
           if (mark) mark[c[u].v] = r.pass + 1;
           mb += c[u].b;
+          mbs += c[u].bs;
           mn++;
         }
       }
     }
   }
   mb = block_sum<kBlock, int64_t>(mb, sms);
+  mbs = block_sum<kBlock, int64_t>(mbs, sms);
   mn = block_sum<kBlock, int64_t>(mn, sms);
   if (threadIdx.x == 0) {
-    finish_pass(rc, mb, mn);
+    finish_pass(rc, mbs, mb, mn);
     *pass_out = rc->pass;
   }
 }
@@ -1273,7 +1284,7 @@ __device__ __forceinline__ void b_refine_settle(int32_t n, int8_t* part, RefCtl*
 __device__ __forceinline__ void b_refine_finish(RefCtl* rc, int32_t* pass_out) {
   if (rc->done) return;
   if (threadIdx.x == 0) {
-    finish_pass(rc, rc->moved_b, rc->moved_n);
+    finish_pass(rc, rc->moved_bs, rc->moved_b, rc->moved_n);
     *pass_out = rc->pass;
   }
 }
@@ -1286,7 +1297,7 @@ __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
   if (rc->done) return;
   const RefCtl r = *rc;
   const int d = 1 - r.s;
-  int64_t mb = 0, mn = 0;
+  int64_t mb = 0, mbs = 0, mn = 0;
   for (int64_t i = (int64_t)bid_ * kBlock + threadIdx.x; i < r.ncand;
        i += (int64_t)nblk_ * kBlock) {
     const Cand c = list[i];
@@ -1294,13 +1305,16 @@ __device__ __forceinline__ void b_refine_apply(int8_t* part, RefCtl* rc,
       part[c.v] = (int8_t)d;
       if (mark) mark[c.v] = r.pass + 1;
       mb += c.b;
+      mbs += c.bs;
       mn++;
     }
   }
   mb = block_sum<kBlock, int64_t>(mb, sml);
+  mbs = block_sum<kBlock, int64_t>(mbs, sml);
   mn = block_sum<kBlock, int64_t>(mn, sml);
   if (threadIdx.x == 0 && (mb || mn)) {
     atomicAdd((unsigned long long*)&rc->moved_b, (unsigned long long)mb);
+    atomicAdd((unsigned long long*)&rc->moved_bs, (unsigned long long)mbs);
     atomicAdd((unsigned long long*)&rc->moved_n, (unsigned long long)mn);
   }
   if (!inline_tail) return;
@@ -1337,9 +1351,9 @@ __device__ __forceinline__ void b_start_level(RefCtl* rc, int npass, int bid_, i
 // weights kept in sext / sinn instead of the rows: one vertex per thread,
 // the same candidates and per-block partials as the gain kernel.
 __device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, const int64_t* b,
-                                              const int64_t* sext, const int64_t* sinn,
-                                              RefCtl* rc, Cand* list, int64_t* partials,
-                                              int bid_, int nblk_) {
+                                              const int64_t* b1, const int64_t* sext,
+                                              const int64_t* sinn, RefCtl* rc, Cand* list,
+                                              int64_t* partials, int bid_, int nblk_) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
   int mode, s;
@@ -1355,15 +1369,16 @@ __device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, con
     c.pad = 0;
     if (v < n) {
       const int8_t pv = part[v];
-      const int64_t ext = sext[v], in = sinn[v], bv = b[v];
+      const int64_t ext = sext[v], in = sinn[v], w0 = b[v], w1 = b1 ? b1[v] : w0;
       const int64_t gain = ext - in;
       ext_acc += ext;
       cand = pv == s && (mode == 1 || gain > 0);
       if (cand) {
         c.gain = gain;
-        c.b = bv;
+        c.b = s ? w0 : w1;
+        c.bs = s ? w1 : w0;
         c.v = (int32_t)v;
-        cb += bv;
+        cb += c.b;
         gmn = gain < gmn ? gain : gmn;
         gmx = gain > gmx ? gain : gmx;
       }
@@ -1586,6 +1601,7 @@ __device__ void refine_block(const LevelView& lv, int8_t* part, RefCtl* rc, Cand
         if (cand) {
           c.gain = gain;
           c.b = lv.b[v];
+          c.bs = c.b;
           c.v = v;
           cb += c.b;
           gmn = gain < gmn ? gain : gmn;
@@ -1622,7 +1638,7 @@ __device__ void refine_block(const LevelView& lv, int8_t* part, RefCtl* rc, Cand
     }
     mb = block_sum<BS, int64_t>(mb, sml);
     mn = block_sum<BS, int64_t>(mn, sml);
-    if (threadIdx.x == 0) finish_pass(rc, mb, mn);
+    if (threadIdx.x == 0) finish_pass(rc, mb, mb, mn);
   }
 }
 
@@ -1851,7 +1867,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
       }
     int64_t unused_min = 0, unused_max = 0;
     block_sum_sum_min_max<BS>(mb, mn, unused_min, unused_max, sm4);
-    if (threadIdx.x == 0) finish_pass(&srf, mb, mn);
+    if (threadIdx.x == 0) finish_pass(&srf, mb, mb, mn);
     __syncthreads();
   }
 }

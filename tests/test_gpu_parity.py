@@ -413,3 +413,25 @@ def test_long_rows_beyond_packed_ids(gp):
     g = dagen.to_csr(n, src[keep], dst[keep], w, vw, "hubs1.1m")
     check_hierarchy(gp, g)
     assert_same(*run_both(gp, g))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_time_balance_matches_oracle(gp, seed):
+    """GP_TIME_BALANCE (each side in its own cost column) on graphs whose
+    per-kernel CPU/GPU ratio varies, every level's trace included."""
+    from test_oracle_time import mixed_cholesky
+    rng = np.random.default_rng(500 + seed)
+    graphs = [mixed_cholesky(int(rng.integers(8, 40)), seed),
+              dagen.layered(int(rng.integers(2000, 80000)), int(rng.integers(4, 30)), rate=3,
+                            seed=seed),
+              random_graph(int(rng.integers(3, 400)), 0.03, rng, wmax=100, vmax=50)]
+    g = graphs[1]
+    g.vwgt = np.stack([g.vwgt[:, 0], rng.integers(1, 5000, g.n)], 1).astype(np.int64)
+    for g in graphs:
+        W0, W1 = int(g.vwgt[:, 0].sum()), int(g.vwgt[:, 1].sum())
+        ratio = (W1, W0)
+        while max(ratio) >= 1 << 40:
+            ratio = (ratio[0] // 2, ratio[1] // 2)
+        kw = dict(ratio=ratio, eps_ppm=int(rng.choice([0, 30000])), flags=oracle.FLAG_TIME,
+                  coarsen_to=int(rng.choice([16, 256, 2048])), balance_on=seed % 2)
+        assert_same(*run_both(gp, g, **kw))
