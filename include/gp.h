@@ -59,8 +59,21 @@ enum {
   GP_HOST_PTRS = 1,  /* input / output pointers are host memory (else device memory) */
   GP_LEARNED = 2,    /* run the learned coarsest-level proposal beside the plain one */
   GP_TRACE = 4,      /* record per-level statistics (costs one extra pass per level) */
-  GP_TIME_BALANCE = 8 /* balance each side in its own cost column (below) */
+  GP_TIME_BALANCE = 8, /* balance each side in its own cost column (below) */
+  GP_VOLUME = 16       /* communication-volume passes on the input graph (below) */
 };
+/* GP_VOLUME: the objective counts each task's output once per memory node
+ * that needs it (Section IV-C's transfer counts; a tile cached on a node is
+ * not sent again) instead of once per cut edge.  The ids must be a
+ * topological order (every dependency points from the smaller id to the
+ * larger); task u's output is as large as its largest edge to a successor,
+ * out(u), and the volume is the sum of out(u) over the tasks with a successor
+ * on the other side.  After the edge-cut refinement of the input graph, up to
+ * refine_passes more passes use the volume gain of a move in place of its
+ * edge-cut gain (same pass plan, order and admission).  res->volume reports
+ * the volume.  Not with GP_LEARNED or GP_TIME_BALANCE, the batched calls or
+ * gp_partition_kway (GP_EINVAL).  gp_level_read's and the trace's level 0
+ * show the bisection before these passes. */
 /* GP_TIME_BALANCE lifts the assumption that every kernel has the same
  * CPU/GPU performance ratio (Section IV-D): side 0 is measured by its CPU
  * cost and side 1 by its GPU cost, each against its own bound tgt_p =
@@ -94,6 +107,7 @@ typedef struct {
   int32_t levels;        /* number of coarse graphs built */
   int32_t used_learned;  /* 1 when the learned proposal beat the plain one */
   int32_t status;        /* gp_status of this graph (batched calls); GP_OK otherwise */
+  int64_t volume;        /* communication volume (GP_VOLUME; 0 otherwise) */
 } gp_result;
 
 /* Fill *o with the defaults: ratio 1:4, eps 3 %, CPU column, seed 0, 2048, 8, 8, 16. */
@@ -317,9 +331,10 @@ void gp_train_destroy(gp_trainer* t);
  * Tasks are placed in id order, which must be a topological order (every
  * dependency u-v points from the smaller id to the larger).  vwgt[v] =
  * (cpu cost, gpu cost) in time units; a dependency between nodes costs one
- * transfer of its edge's bytes over a single link (latency + ceil(bytes /
- * bw) time units, transfers in request order), made once per producer and
- * destination node.  All pointers are host memory; task_node (int8[n]) and
+ * transfer of the producer's output (as large as its largest edge to a
+ * successor) over a single link (latency + ceil(bytes / bw) time units,
+ * transfers in request order), made once per producer and destination
+ * node.  All pointers are host memory; task_node (int8[n]) and
  * task_finish (int64[n]) may be NULL.
  * --------------------------------------------------------------------- */
 enum { GP_SIM_EAGER = 0, GP_SIM_DMDA = 1, GP_SIM_GP = 2 };

@@ -20,6 +20,7 @@ _lib = None
 OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)
 FLAG_LEARNED = 2
 FLAG_TIME = 8
+FLAG_VOLUME = 16
 
 
 def build(extra_flags=()) -> str:
@@ -53,6 +54,8 @@ def _load():
     lib.or_match_twohop.argtypes = [i32, vp, vp, vp, vp, i64, u64, i32, vp]
     lib.or_contract.restype = i32
     lib.or_contract.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_volume.restype = i64
+    lib.or_volume.argtypes = [i32, vp, vp, vp, vp]
     lib.or_cut.restype = i64
     lib.or_cut.argtypes = [i32, vp, vp, vp, vp]
     lib.or_refine.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
@@ -113,6 +116,7 @@ class Result:
     levels: int
     used_learned: int
     trace: np.ndarray
+    volume: int = 0
 
 
 def ratio_from_times(t_cpu: int, t_gpu: int):
@@ -193,6 +197,16 @@ def cut(n, xadj, adjncy, adjwgt, part) -> int:
                               _p(_c(adjwgt, np.int64)), _p(_c(part, np.int8))))
 
 
+def volume(graph, part) -> int:
+    """Communication volume of a two-way part vector: every task's output (as
+    large as its largest edge to a successor) counted once when a successor
+    lies on the other side."""
+    adj = _c(graph.adjncy if len(graph.adjncy) else np.zeros(1), np.int32)
+    w = _c(graph.adjwgt if len(graph.adjwgt) else np.zeros(1), np.int64)
+    return int(_load().or_volume(graph.n, _p(_c(graph.xadj, np.int32)), _p(adj), _p(w),
+                                 _p(_c(part, np.int8))))
+
+
 def refine(n, xadj, adjncy, adjwgt, b, part, pw, maxw, passes):
     part = _c(part, np.int8).copy()
     pw = _c(pw, np.int64).copy()
@@ -228,7 +242,7 @@ def partition(graph=None, opts: Options | None = None, *, n=None, xadj=None, adj
     if vwgt.size == 0:
         vwgt = np.zeros(2, np.int64)
     part = np.zeros(max(n, 1), np.int8)
-    res = np.zeros(8, np.int64)
+    res = np.zeros(9, np.int64)
     trace = np.zeros(8 * trace_cap, np.int64)
     mp = None
     if model is not None:
@@ -238,7 +252,7 @@ def partition(graph=None, opts: Options | None = None, *, n=None, xadj=None, adj
     levels = int(res[6])
     tr = trace.reshape(trace_cap, 8)[:levels + 1].copy() if rc == OK and n > 0 else trace[:0]
     return Result(rc, part[:n].copy(), int(res[0]), (int(res[1]), int(res[2])),
-                  (int(res[3]), int(res[4])), int(res[5]), levels, int(res[7]), tr)
+                  (int(res[3]), int(res[4])), int(res[5]), levels, int(res[7]), tr, int(res[8]))
 
 
 # ------------------------------------------------------------ learned part

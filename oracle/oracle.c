@@ -497,6 +497,130 @@ static int refine_og(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Communication volume (a reading of "count a tile once per memory node"):  */
+/* the graph's ids are a topological order, so the successors of u are its  */
+/* neighbours with larger ids; u's output is as large as its largest edge to */
+/* a successor, out(u), and crosses to the other part once when any          */
+/* successor lies there.  vol = sum over u of out(u) [a successor of u is on  */
+/* the other side].                                                          */
+/* ------------------------------------------------------------------------ */
+static OG og_view(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                  const int64_t* vc, const int64_t* vg);
+
+static void vol_out(const OG* g, int64_t* out) {
+  for (int32_t u = 0; u < g->n; u++) {
+    out[u] = 0;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (g->adj[e] > u && g->w[e] > out[u]) out[u] = g->w[e];
+  }
+}
+
+/* successors of u on the other side of u */
+static void vol_ext_succ(const OG* g, const int8_t* part, int32_t* cnt) {
+  for (int32_t u = 0; u < g->n; u++) {
+    cnt[u] = 0;
+    for (int32_t e = g->xadj[u]; e < g->xadj[u + 1]; e++)
+      if (g->adj[e] > u && part[g->adj[e]] != part[u]) cnt[u]++;
+  }
+}
+
+int64_t or_volume(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
+                  const int8_t* part) {
+  OG g = og_view(n, xadj, adj, w, NULL, NULL);
+  int64_t* out = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!out || !cnt) { free(out); free(cnt); return -1; }
+  vol_out(&g, out);
+  vol_ext_succ(&g, part, cnt);
+  int64_t vol = 0;
+  for (int32_t u = 0; u < n; u++)
+    if (cnt[u] > 0) vol += out[u];
+  free(out);
+  free(cnt);
+  return vol;
+}
+
+/* The volume gain of moving v from its side s to d, at the pass's start:
+   v's own output stops crossing when no successor is left on d and starts
+   crossing when one is on s; a predecessor u on d whose only successor on
+   the other side was v stops crossing; a predecessor u on s with no
+   successor on the other side starts crossing. */
+static int64_t vol_gain(const OG* g, const int8_t* part, const int64_t* out, const int32_t* cnt,
+                        int32_t v) {
+  const int s = part[v], d = 1 - s;
+  int32_t succ_s = 0, succ_d = 0;
+  int64_t gain = 0;
+  for (int32_t e = g->xadj[v]; e < g->xadj[v + 1]; e++) {
+    const int32_t x = g->adj[e];
+    if (x > v) {
+      if (part[x] == s) succ_s++;
+      else succ_d++;
+    } else if (x < v) {
+      if (part[x] == d && cnt[x] == 1) gain += out[x];
+      if (part[x] == s && cnt[x] == 0) gain -= out[x];
+    }
+  }
+  gain += out[v] * ((succ_d > 0) - (succ_s > 0));
+  return gain;
+}
+
+/* At most P passes of the refinement rules with the volume gain in place of
+   the edge-cut gain (same pass plan, candidate order and admission). */
+static int refine_vol(const OG* g, const int64_t* b, int8_t* part, int64_t* pw,
+                      const int64_t* maxw, int P) {
+  int32_t n = g->n;
+  int64_t* out = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  Cand* list = (Cand*)malloc(sizeof(Cand) * (size_t)(n > 0 ? n : 1));
+  if (!out || !cnt || !list) { free(out); free(cnt); free(list); return -1; }
+  vol_out(g, out);
+  int z = 0;
+  for (int i = 0; i < P; i++) {
+    vol_ext_succ(g, part, cnt);
+    int over = pw[0] > maxw[0] ? 0 : (pw[1] > maxw[1] ? 1 : -1);
+    int s = over >= 0 ? over : (i & 1), d = 1 - s;
+    int32_t k = 0;
+    for (int32_t v = 0; v < n; v++) {
+      if (part[v] != s) continue;
+      const int64_t gn = vol_gain(g, part, out, cnt, v);
+      if (over >= 0 || gn > 0) {
+        list[k].v = v; list[k].gain = gn; list[k].b = b[v]; list[k].bs = b[v];
+        k++;
+      }
+    }
+    qsort(list, (size_t)k, sizeof(Cand), cand_cmp);
+    int64_t budget = maxw[d] - pw[d];
+    int32_t take = 0;
+    int64_t acc = 0;
+    if (over >= 0) {
+      int64_t excess = pw[s] - maxw[s];
+      int32_t k1 = 0;
+      while (k1 < k && acc < excess) { acc += list[k1].b; k1++; }
+      int32_t k2 = 0;
+      acc = 0;
+      while (k2 < k && acc + list[k2].b <= budget) { acc += list[k2].b; k2++; }
+      take = k1 < k2 ? k1 : k2;
+    } else {
+      while (take < k && acc + list[take].b <= budget) { acc += list[take].b; take++; }
+    }
+    for (int32_t j = 0; j < take; j++) {
+      part[list[j].v] = (int8_t)d;
+      pw[s] -= list[j].b;
+      pw[d] += list[j].b;
+    }
+    if (over >= 0) z = 0;
+    else {
+      z = take == 0 ? z + 1 : 0;
+      if (z == 2) break;
+    }
+  }
+  free(out);
+  free(cnt);
+  free(list);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Initial bisection at the coarsest level by greedy graph growing.          */
 /* The grown side g is the part with the smaller ratio (part 0 on a tie);    */
 /* the other side is gb.  K = min(trials, n) trials; trial t starts with all */
@@ -650,6 +774,7 @@ int or_init_bisect(int32_t n, const int32_t* xadj, const int32_t* adj, const int
 /* res:  [0] cut  [1..2] part weights (balance column)  [3] CPU time of part */
 /*       0 (cpu costs)  [4] GPU time of part 1 (gpu costs)  [5] feasible     */
 /*       [6] levels  [7] learned result kept (judged on the input graph)    */
+/*       [8] communication volume (with the volume objective, else 0)        */
 /* trace (optional, 8 int64 per level, level 0 first): n, nnz, passes,       */
 /*       moves, cut after refinement, pw0, pw1, pairs matched on this level  */
 /* Coarsening runs while n > C, and stops after a level that removed less   */
@@ -707,6 +832,10 @@ static int uncoarsen(OG* lv, int32_t* const* cmap, int L, int bal, int time_mode
    usual; from the coarsest level on, the refinement works with the two
    columns, its rebalance passes bringing each side under its own bound. */
 #define OR_FLAG_TIME 8
+/* Communication-volume objective: after the edge-cut refinement of the input
+   graph, at most P more passes with the volume gain (vol_gain); the result
+   then also reports the volume. */
+#define OR_FLAG_VOLUME 16
 
 int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64_t* w,
                  const int64_t* vwgt, const int64_t* opts, const void* model, int8_t* part_out,
@@ -721,6 +850,7 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
   if (C < 1 || R < 0 || R > 64 || P < 0 || P > 64 || K < 1 || K > 64) return OR_EINVAL;
   if ((flags & OR_FLAG_LEARNED) && !model) return OR_EMODEL;
   if ((flags & OR_FLAG_LEARNED) && (flags & OR_FLAG_TIME)) return OR_EINVAL;
+  if ((flags & OR_FLAG_VOLUME) && (flags & (OR_FLAG_LEARNED | OR_FLAG_TIME))) return OR_EINVAL;
   const int time_mode = (flags & OR_FLAG_TIME) != 0;
   if (n < 0) return OR_EINVAL;
 
@@ -832,6 +962,13 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
   }
   free(lp);
   free(ltrace);
+  int64_t volume = 0;
+  if (rc == OR_OK && (flags & OR_FLAG_VOLUME) && n > 0) {
+    OG* g = &lv[0];
+    if (refine_vol(g, bal ? g->vg : g->vc, part, pw, maxw, (int)P) < 0) rc = OR_ENOMEM;
+    if (rc == OR_OK) volume = or_volume(n, g->xadj, g->adj, g->w, part);
+    if (volume < 0) rc = OR_ENOMEM;
+  }
   if (rc == OR_OK) {
     OG* g = &lv[0];
     int64_t tc = 0, tg = 0;
@@ -847,6 +984,7 @@ int or_partition(int32_t n, const int32_t* xadj, const int32_t* adj, const int64
     res[5] = pw[0] <= maxw[0] && pw[1] <= maxw[1];
     res[6] = L;
     res[7] = used_learned;
+    res[8] = volume;
   }
   free(part);
   for (int l = 0; l <= L; l++) og_free(&lv[l]);

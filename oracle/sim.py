@@ -7,10 +7,11 @@ policy (the node the partition names).  Reading taken here: tasks are placed
 one by one in id order (a topological order: dependencies point from the
 smaller id to the larger); a task starts when its worker is free and its
 inputs are on its node; a dependency across nodes costs one transfer of the
-edge's bytes over a single link (latency + ceil(bytes / bw), transfers in the
+producer's output over a single link (latency + ceil(bytes / bw), transfers in the
 order they are asked for, each starting when the link is free and the
-producer has finished); the first transfer of a producer's output to a node
-serves every later consumer there.  Ties go to GPU workers first, then to
+producer has finished); the data a task produces is as large as its largest
+edge to a successor, and its first transfer to a node serves every later
+consumer there.  Ties go to GPU workers first, then to
 the lower worker index.  Plain Python.
 """
 from __future__ import annotations
@@ -46,6 +47,9 @@ def simulate(graph, policy: int, part=None, ncpu: int = 3, ngpu: int = 1, latenc
     node = [0] * n
     arrived = {}                              # (producer, node) -> arrival time
     state = {"link": 0, "transfers": 0, "bytes": 0}
+    # size of each task's output: its largest edge to a successor
+    out = [max([w[e] for e in range(xadj[u], xadj[u + 1]) if adj[e] > u], default=0)
+           for u in range(n)]
 
     def ready_on(v, p, commit):
         t, link = 0, state["link"]
@@ -58,12 +62,12 @@ def simulate(graph, policy: int, part=None, ncpu: int = 3, ngpu: int = 1, latenc
             elif (u, p) in arrived:
                 at = arrived[(u, p)]
             else:
-                at = max(link, fin[u]) + latency + -(-w[e] // bw)
+                at = max(link, fin[u]) + latency + -(-out[u] // bw)
                 link = at
                 if commit:
                     arrived[(u, p)] = at
                     state["transfers"] += 1
-                    state["bytes"] += w[e]
+                    state["bytes"] += out[u]
             t = max(t, at)
         if commit:
             state["link"] = link

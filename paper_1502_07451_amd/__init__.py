@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgp.so")
 
 OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)
-HOST_PTRS, LEARNED, TRACE, TIME_BALANCE = 1, 2, 4, 8
+HOST_PTRS, LEARNED, TRACE, TIME_BALANCE, VOLUME = 1, 2, 4, 8, 16
 
 
 class GPError(RuntimeError):
@@ -44,12 +44,13 @@ class Result(ctypes.Structure):
     _fields_ = [("cut", ctypes.c_int64), ("load", ctypes.c_int64 * 2),
                 ("time", ctypes.c_int64 * 2), ("feasible", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("used_learned", ctypes.c_int32),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("volume", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return dict(cut=self.cut, load=(self.load[0], self.load[1]),
                     time=(self.time[0], self.time[1]), feasible=self.feasible,
-                    levels=self.levels, used_learned=self.used_learned, status=self.status)
+                    levels=self.levels, used_learned=self.used_learned, status=self.status,
+                    volume=self.volume)
 
 
 class KwayResult(ctypes.Structure):

@@ -619,7 +619,7 @@ static gp_status batch_options(const gp_options* o) {
       o->refine_passes < 0 || o->refine_passes > 64 || o->init_trials < 1 || o->init_trials > 64)
     return GP_EINVAL;
   if (o->flags & GP_LEARNED) return GP_EMODEL;
-  if (o->flags & GP_TIME_BALANCE) return GP_EINVAL;
+  if (o->flags & (GP_TIME_BALANCE | GP_VOLUME)) return GP_EINVAL;
   return GP_OK;
 }
 

@@ -286,6 +286,7 @@ static gp_status check_options(const gp_options* o) {
     if (!m || m->magic != kMpMagic) return GP_EMODEL;
     if (o->flags & GP_TIME_BALANCE) return GP_EINVAL;
   }
+  if ((o->flags & GP_VOLUME) && (o->flags & (GP_LEARNED | GP_TIME_BALANCE))) return GP_EINVAL;
   return GP_OK;
 }
 
@@ -644,6 +645,23 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   if ((st = uncoarsen(trace)) != GP_OK) return st;
   for (int l = L - 1; l >= 0; l--) prof_mark(g, l, false);
   Level* l0 = g->lv[0];
+  int64_t volume = 0;
+  if (o->flags & GP_VOLUME) {
+    // communication-volume passes on the input graph after its edge-cut
+    // refinement; r_ext holds each task's output size, r_mark the counts of
+    // successors on the other side
+    const LevelView v0 = l0->view(bal);
+    const int tw = team_width_for(l0->n, l0->nnz);
+    LCHK(launch_vol_out(v0, g->r_ext.p, tw, s));
+    LCHK(launch_start_level(&g->ctrl->ref, P, s));
+    for (int p = 0; p < P; p++)
+      LCHK(launch_vol_pass(v0, l0->part.p, &g->ctrl->ref, sc.list, sc.partials,
+                           &g->ctrl->lvl_pass[0], g->r_ext.p, g->r_mark.p, tw, s));
+    LCHK(launch_final_stats(v0, l0->vc.p, l0->vg.p, l0->part.p, g->ctrl, tw, sc.partials, s));
+    LCHK(launch_vol_total(v0, l0->part.p, g->r_ext.p, g->ctrl, tw, s));
+    if ((st = read_ctrl(g)) != GP_OK) return st;
+    volume = h.res_vol;
+  }
   int used_learned = 0;
   if (learned) {
     // the plain bisection judges the learned one on the input graph: the
@@ -685,6 +703,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   g->last_levels = L;
   r.used_learned = used_learned;
   r.status = GP_OK;
+  r.volume = volume;
   *res = r;
   return GP_OK;
 }
@@ -769,7 +788,7 @@ gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const 
   o2.ratio[0] = 1;
   o2.ratio[1] = 1;
   if (o2.flags & GP_LEARNED) return GP_EMODEL;
-  if (o2.flags & GP_TIME_BALANCE) return GP_EINVAL;
+  if (o2.flags & (GP_TIME_BALANCE | GP_VOLUME)) return GP_EINVAL;
   gp_status st = check_options(&o2);
   if (st != GP_OK) return st;
   const int32_t n = g->n;

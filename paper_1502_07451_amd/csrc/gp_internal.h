@@ -86,6 +86,7 @@ struct Ctrl {
   int64_t lpw[2];                    // part weights of the refined learned proposal
   // result of the final statistics kernel
   int64_t res_ext, res_load[2], res_time[2];
+  int64_t res_vol;        // communication volume (volume objective)
   // validation
   uint32_t verr;          // bit flags
   uint32_t vunsorted;

@@ -212,6 +212,34 @@ __global__ __launch_bounds__(kBlock) void k_project(int32_t n, const int32_t* cm
   b_project(n, cmap, cpart, part, rc, npass, (int)blockIdx.x, (int)gridDim.x, mark);
 }
 
+template <int TW>
+__global__ __launch_bounds__(kBlock) void k_vol_out(LevelView lv, int64_t* out) {
+  b_vol_out<TW>(lv, out, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <int TW>
+__global__ __launch_bounds__(kBlock) void k_vol_count(LevelView lv, const int8_t* part,
+                                                      int32_t* cnt) {
+  b_vol_count<TW>(lv, part, cnt, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <int TW>
+__global__ __launch_bounds__(kBlock) void k_vol_gain(LevelView lv, const int8_t* part,
+                                                     const int64_t* out, const int32_t* cnt,
+                                                     RefCtl* rc, Cand* list, int64_t* partials) {
+  b_vol_gain<TW>(lv, part, out, cnt, rc, list, partials, (int)blockIdx.x, (int)gridDim.x);
+}
+
+__global__ void k_vol_reset(Ctrl* ctrl) {
+  if (threadIdx.x == 0) ctrl->res_vol = 0;
+}
+
+template <int TW>
+__global__ __launch_bounds__(kBlock) void k_vol_total(LevelView lv, const int8_t* part,
+                                                      const int64_t* out, Ctrl* ctrl) {
+  b_vol_total<TW>(lv, part, out, &ctrl->res_vol, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // time balance: the loads become (CPU cost of side 0, GPU cost of side 1),
 // taken from the statistics kernel, with their own bounds; a new pass sequence
 __global__ void k_time_bounds(Ctrl* ctrl, int64_t maxw0, int64_t maxw1, int npass) {
@@ -568,6 +596,84 @@ static bool delta_tw(const LevelView& lv, const int8_t* part, const RefCtl* rc, 
   return true;
 }
 
+// decision, moves and pass bookkeeping after a candidate launch of `grid`
+// blocks: one block on levels of at most kSettleMax vertices, else decide ->
+// apply -> finish
+static bool pass_tail(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                      int64_t* partials, int grid, int32_t* pass_out, int32_t* mark,
+                      hipStream_t s) {
+  if (lv.n <= kSettleMax) {
+    ProfScope ps(PK_REFINE_SETTLE, 0, 0.0, s);
+    k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out, mark);
+    KCHECK();
+    return true;
+  }
+  k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
+  KCHECK();
+  {
+    ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
+    k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list, pass_out,
+                                                                       mark);
+  }
+  KCHECK();
+  k_refine_finish<<<1, 64, 0, s>>>(rc, pass_out);
+  KCHECK();
+  return true;
+}
+
+template <int TW>
+static bool vol_pass_tw(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                        int64_t* partials, int32_t* pass_out, const int64_t* out, int32_t* cnt,
+                        hipStream_t s) {
+  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
+  k_vol_count<TW><<<grid, kBlock, 0, s>>>(lv, part, cnt);
+  KCHECK();
+  k_vol_gain<TW><<<grid, kBlock, 0, s>>>(lv, part, out, cnt, rc, list, partials);
+  KCHECK();
+  return pass_tail(lv, part, rc, list, partials, grid, pass_out, nullptr, s);
+}
+
+bool launch_vol_out(const LevelView& lv, int64_t* out, int tw, hipStream_t s) {
+  const int grid = grid_for((int64_t)lv.n * tw, kBlock);
+  switch (tw) {
+    case 4: k_vol_out<4><<<grid, kBlock, 0, s>>>(lv, out); break;
+    case 8: k_vol_out<8><<<grid, kBlock, 0, s>>>(lv, out); break;
+    case 16: k_vol_out<16><<<grid, kBlock, 0, s>>>(lv, out); break;
+    case 32: k_vol_out<32><<<grid, kBlock, 0, s>>>(lv, out); break;
+    default: k_vol_out<64><<<grid, kBlock, 0, s>>>(lv, out); break;
+  }
+  KCHECK();
+  return true;
+}
+
+bool launch_vol_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                     int64_t* partials, int32_t* pass_out, const int64_t* out, int32_t* cnt,
+                     int tw, hipStream_t s) {
+  switch (tw) {
+    case 4: return vol_pass_tw<4>(lv, part, rc, list, partials, pass_out, out, cnt, s);
+    case 8: return vol_pass_tw<8>(lv, part, rc, list, partials, pass_out, out, cnt, s);
+    case 16: return vol_pass_tw<16>(lv, part, rc, list, partials, pass_out, out, cnt, s);
+    case 32: return vol_pass_tw<32>(lv, part, rc, list, partials, pass_out, out, cnt, s);
+    default: return vol_pass_tw<64>(lv, part, rc, list, partials, pass_out, out, cnt, s);
+  }
+}
+
+bool launch_vol_total(const LevelView& lv, const int8_t* part, const int64_t* out, Ctrl* ctrl,
+                      int tw, hipStream_t s) {
+  k_vol_reset<<<1, 64, 0, s>>>(ctrl);
+  KCHECK();
+  const int grid = grid_for((int64_t)lv.n * tw, kBlock);
+  switch (tw) {
+    case 4: k_vol_total<4><<<grid, kBlock, 0, s>>>(lv, part, out, ctrl); break;
+    case 8: k_vol_total<8><<<grid, kBlock, 0, s>>>(lv, part, out, ctrl); break;
+    case 16: k_vol_total<16><<<grid, kBlock, 0, s>>>(lv, part, out, ctrl); break;
+    case 32: k_vol_total<32><<<grid, kBlock, 0, s>>>(lv, part, out, ctrl); break;
+    default: k_vol_total<64><<<grid, kBlock, 0, s>>>(lv, part, out, ctrl); break;
+  }
+  KCHECK();
+  return true;
+}
+
 bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
                         int64_t* partials, int tw, int32_t* pass_out, int p, int npass,
                         const RefArrays& ra, hipStream_t s) {
@@ -591,24 +697,7 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
                                           partials);
     KCHECK();
   }
-  if (lv.n <= kSettleMax) {
-    // decision, moves and pass bookkeeping in one single-block launch
-    ProfScope ps(PK_REFINE_SETTLE, 0, 0.0, s);
-    k_refine_settle<<<1, kBlock, 0, s>>>(lv.n, part, rc, list, partials, grid, pass_out,
-                                         ra.mark);
-    KCHECK();
-  } else {
-    k_refine_decide<<<1, kBlock, 0, s>>>(lv.n, rc, list, partials, grid);
-    KCHECK();
-    {
-      ProfScope ps(PK_REFINE_APPLY, 0, 0.0, s);
-      k_refine_apply<<<grid_for(lv.n, kBlock * 8, 1024), kBlock, 0, s>>>(part, rc, list,
-                                                                         pass_out, ra.mark);
-    }
-    KCHECK();
-    k_refine_finish<<<1, 64, 0, s>>>(rc, pass_out);
-    KCHECK();
-  }
+  if (!pass_tail(lv, part, rc, list, partials, grid, pass_out, ra.mark, s)) return false;
   if (p + 1 >= npass) return true;  // no pass reads the weights after the last one
   switch (tw) {
     case 4: return delta_tw<4>(lv, part, rc, list, ra, p, s);

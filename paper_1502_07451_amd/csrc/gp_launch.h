@@ -101,6 +101,15 @@ bool launch_refine_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* lis
 bool launch_project(int32_t n, const int32_t* cmap, const int8_t* cpart, int8_t* part, RefCtl* rc,
                     int npass, int32_t* mark, hipStream_t s);
 bool launch_start_level(RefCtl* rc, int npass, hipStream_t s);
+// communication volume: out = each vertex's largest edge to a successor; one
+// pass with the volume gain (cnt: int32[n] scratch); the volume into
+// ctrl->res_vol
+bool launch_vol_out(const LevelView& lv, int64_t* out, int tw, hipStream_t s);
+bool launch_vol_pass(const LevelView& lv, int8_t* part, RefCtl* rc, Cand* list,
+                     int64_t* partials, int32_t* pass_out, const int64_t* out, int32_t* cnt,
+                     int tw, hipStream_t s);
+bool launch_vol_total(const LevelView& lv, const int8_t* part, const int64_t* out, Ctrl* ctrl,
+                      int tw, hipStream_t s);
 // time balance: loads from the last statistics launch, bounds (maxw0, maxw1)
 bool launch_time_bounds(Ctrl* ctrl, int64_t maxw0, int64_t maxw1, int npass, hipStream_t s);
 // partials: 5 int64 per block (grids are capped at 4096)

@@ -1443,6 +1443,151 @@ __device__ __forceinline__ void b_refine_delta(LevelView lv, const int8_t* part,
   }
 }
 
+// ------------------------------------------------------ communication volume
+// The ids of the input graph are a topological order, so the successors of
+// v are its neighbours with larger ids.  v's output is as large as its
+// largest edge to a successor, out(v), and crosses to the other side once
+// when any successor lies there; the volume is the sum of the outputs that
+// cross.
+
+// out(v) for every vertex (one team per row)
+template <int TW>
+__device__ __forceinline__ void b_vol_out(LevelView lv, int64_t* out, int bid_, int nblk_) {
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t vv = team; vv < lv.n; vv += nteams) {
+    const int32_t v = (int32_t)vv;
+    int64_t m = 0;
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW)
+      if (lv.adj[e] > v && lv.w[e] > m) m = lv.w[e];
+    m = team_max<TW, int64_t>(m);
+    if (lane == 0) out[v] = m;
+  }
+}
+
+// successors of v on the other side of v
+template <int TW>
+__device__ __forceinline__ void b_vol_count(LevelView lv, const int8_t* part, int32_t* cnt,
+                                            int bid_, int nblk_) {
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  for (int64_t vv = team; vv < lv.n; vv += nteams) {
+    const int32_t v = (int32_t)vv;
+    const int8_t pv = part[v];
+    int32_t c = 0;
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+      const int32_t x = lv.adj[e];
+      c += x > v && part[x] != pv;
+    }
+    c = team_sum<TW, int32_t>(c);
+    if (lane == 0) cnt[v] = c;
+  }
+}
+
+// A volume pass's candidates: the gain of moving v from its side s to d at
+// the pass's start is out(v) ([a successor on d] - [a successor on s]), plus
+// out(u) for each predecessor u on d whose only successor on the other side
+// is v, minus out(u) for each predecessor u on s with no successor on the
+// other side.  Same list, partials and pass plan as the gain kernel.
+template <int TW>
+__device__ __forceinline__ void b_vol_gain(LevelView lv, const int8_t* part, const int64_t* out,
+                                           const int32_t* cnt, RefCtl* rc, Cand* list,
+                                           int64_t* partials, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  if (rc->done) return;
+  int mode, s;
+  plan_pass(*rc, &mode, &s);
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  int64_t ext_acc = 0, cb = 0, gmn = INT64_MAX, gmx = INT64_MIN;
+  const int64_t iters = (lv.n + nteams - 1) / nteams;
+  for (int64_t it = 0; it < iters; it++) {
+    const int64_t uu = team + it * nteams;
+    bool cand = false;
+    Cand c;
+    c.pad = 0;
+    if (uu < lv.n) {
+      const int32_t v = (int32_t)uu;
+      const int8_t pv = part[v];
+      int64_t ext = 0, pred = 0;
+      int32_t succ_s = 0, succ_d = 0;
+      for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+        const int32_t x = lv.adj[e];
+        const int8_t px = part[x];
+        if (px != pv) ext += lv.w[e];
+        if (x > v) {
+          if (px == pv) succ_s++;
+          else succ_d++;
+        } else {
+          const int32_t cx = cnt[x];
+          if (px != pv && cx == 1) pred += out[x];
+          if (px == pv && cx == 0) pred -= out[x];
+        }
+      }
+      ext = team_sum<TW>(ext);
+      pred = team_sum<TW>(pred);
+      succ_s = team_sum<TW, int32_t>(succ_s);
+      succ_d = team_sum<TW, int32_t>(succ_d);
+      if (lane == 0) {
+        const int64_t gain = pred + out[v] * ((succ_d > 0 ? 1 : 0) - (succ_s > 0 ? 1 : 0));
+        ext_acc += ext;
+        cand = pv == s && (mode == 1 || gain > 0);
+        if (cand) {
+          c.gain = gain;
+          c.b = lv.b[v];
+          c.bs = c.b;
+          c.v = v;
+          cb += c.b;
+          gmn = gain < gmn ? gain : gmn;
+          gmx = gain > gmx ? gain : gmx;
+        }
+      }
+    }
+    append_cand(cand, c, list, &rc->ncand);
+  }
+  ext_acc = block_sum<kBlock, int64_t>(ext_acc, sml);
+  cb = block_sum<kBlock, int64_t>(cb, sml);
+  gmn = block_min<kBlock, int64_t>(gmn, sml);
+  gmx = block_max<kBlock, int64_t>(gmx, sml);
+  if (threadIdx.x == 0) {
+    partials[4 * bid_ + 0] = ext_acc;
+    partials[4 * bid_ + 1] = cb;
+    partials[4 * bid_ + 2] = gmn;
+    partials[4 * bid_ + 3] = gmx;
+  }
+}
+
+// the volume of the current assignment, added to *vol (integer atomics)
+template <int TW>
+__device__ __forceinline__ void b_vol_total(LevelView lv, const int8_t* part, const int64_t* out,
+                                            int64_t* vol, int bid_, int nblk_) {
+  __shared__ int64_t sml[kBlock / 64];
+  const int lane = threadIdx.x & (TW - 1);
+  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
+  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
+  int64_t acc = 0;
+  const int64_t iters = (lv.n + nteams - 1) / nteams;
+  for (int64_t it = 0; it < iters; it++) {
+    const int64_t vv = team + it * nteams;
+    int32_t c = 0;
+    if (vv < lv.n) {
+      const int32_t v = (int32_t)vv;
+      const int8_t pv = part[v];
+      for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+        const int32_t x = lv.adj[e];
+        c += x > v && part[x] != pv;
+      }
+    }
+    c = team_sum<TW, int32_t>(c);
+    if (lane == 0 && vv < lv.n && c > 0) acc += out[vv];
+  }
+  acc = block_sum<kBlock, int64_t>(acc, sml);
+  if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long*)vol, (unsigned long long)acc);
+}
+
 // cut (as sum of ext), loads and times of the final assignment
 template <int TW>
 __device__ __forceinline__ void b_final_stats(LevelView lv, const int64_t* vc,

@@ -21,8 +21,8 @@
 //     the other node needs a transfer over one link (one copy engine: the
 //     transfers queue in the order they are requested), which takes
 //     latency + ceil(bytes / bw) and starts once the link is free and u has
-//     finished; the first transfer of u's output to a node (with the bytes of
-//     the edge that asked for it) serves every later consumer on that node;
+//     finished; u's output is as large as u's largest edge to a successor,
+//     and its first transfer to a node serves every later consumer there;
 //   * eager: the worker that is free first (ties: GPU workers before CPU
 //     workers, lower index first); dmda: the worker on which the task would
 //     finish first, counting the transfers it would need (same ties); gp:
@@ -44,6 +44,7 @@ struct SimState {
   const int64_t* w;
   int64_t latency, bw;
   std::vector<int64_t> fin;
+  std::vector<int64_t> out;  // size of each task's output: its largest successor edge
   std::vector<int8_t> node;
   // (producer, node) -> arrival time of its output on that node
   std::unordered_map<int64_t, int64_t> arrived;
@@ -69,12 +70,12 @@ struct SimState {
           at = it->second;
         } else {
           const int64_t start = link > fin[u] ? link : fin[u];
-          at = start + xfer_time(w[e]);
+          at = start + xfer_time(out[u]);
           link = at;
           if (commit) {
             arrived.emplace(key, at);
             transfers++;
-            bytes += w[e];
+            bytes += out[u];
           }
         }
       }
@@ -113,6 +114,10 @@ gp_status gp_simulate(int32_t n, const int32_t* xadj, const int32_t* adjncy,
   S.bw = bw;
   S.fin.assign((size_t)n, 0);
   S.node.assign((size_t)n, 0);
+  S.out.assign((size_t)n, 0);
+  for (int32_t u = 0; u < n; u++)
+    for (int32_t e = xadj[u]; e < xadj[u + 1]; e++)
+      if (adjncy[e] > u && adjwgt[e] > S.out[u]) S.out[u] = adjwgt[e];
   // workers: GPU workers first (the tie order), then CPU workers
   const int nw = ngpu + ncpu;
   std::vector<int64_t> avail((size_t)nw, 0);

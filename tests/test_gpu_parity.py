@@ -435,3 +435,21 @@ def test_time_balance_matches_oracle(gp, seed):
         kw = dict(ratio=ratio, eps_ppm=int(rng.choice([0, 30000])), flags=oracle.FLAG_TIME,
                   coarsen_to=int(rng.choice([16, 256, 2048])), balance_on=seed % 2)
         assert_same(*run_both(gp, g, **kw))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_volume_objective_matches_oracle(gp, seed):
+    """GP_VOLUME: the volume passes on the input graph and the reported volume
+    equal the oracle's."""
+    rng = np.random.default_rng(700 + seed)
+    graphs = [dagen.layered(int(rng.integers(2000, 120000)), int(rng.integers(4, 40)), rate=3,
+                            seed=seed),
+              dagen.cholesky(int(rng.integers(8, 30)), 512, jitter_pm=100, seed=seed),
+              random_graph(int(rng.integers(3, 400)), 0.03, rng, wmax=1000, vmax=50)]
+    for g in graphs:
+        kw = dict(ratio=(1, int(rng.integers(1, 5))), eps_ppm=int(rng.choice([0, 30000, 100000])),
+                  flags=oracle.FLAG_VOLUME, coarsen_to=int(rng.choice([16, 2048])),
+                  balance_on=seed % 2)
+        ref, got, res, tr = run_both(gp, g, **kw)
+        assert_same(ref, got, res, tr)
+        assert res.volume == ref.volume == oracle.volume(g, ref.part)
