@@ -159,6 +159,22 @@ gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, in
 
 void gp_destroy(gp_graph* g);
 
+/* Device-memory budget of a handle, for callers that share one GPU among
+ * several handles or other work.  A handle holds its copy of the graph and
+ * scratch buffers sized to the levels it builds (a fixed control block of a
+ * few hundred bytes aside); buffers grow on demand and are kept for the next
+ * call.  bytes = -1 (the default) sets no limit; bytes >= 0 makes a call
+ * that would grow the handle's buffers past it return GP_ENOMEM before it
+ * grows them.  A call refused this way may have launched part of its work
+ * and leaves gp_level_read nothing to read; the buffers already held stay
+ * valid, so the same call with a larger limit then succeeds with the same
+ * result.  A k-way partition charges its subgraphs' buffers to the handle.
+ * The limit never frees memory already held.  bytes < -1: GP_EINVAL. */
+gp_status gp_set_workspace_limit(gp_graph* g, int64_t bytes);
+
+/* Device bytes the handle's buffers hold now (-1 for a null handle). */
+int64_t gp_workspace_bytes(const gp_graph* g);
+
 /* ---------------------------------------------------------------------
  * k-way partition (CPU + GPU + further processors).  The paper leaves more
  * than two processors to future work (Section VI) and gives each processor

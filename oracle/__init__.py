@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# GP_ORACLE_LIB names another build of the same sources (the sanitizer test)
+_LIB_PATH = os.environ.get("GP_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, EINVAL, EASYM, EDUP, ESELF, ERANGE, EOVERFLOW, ENOMEM, EDEVICE, EMODEL = range(10)

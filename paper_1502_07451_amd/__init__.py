@@ -117,6 +117,10 @@ def _load():
     lib.gp_partition_trace.restype = ctypes.c_int
     lib.gp_destroy.argtypes = [vp]
     lib.gp_destroy.restype = None
+    lib.gp_set_workspace_limit.argtypes = [vp, i64]
+    lib.gp_set_workspace_limit.restype = ctypes.c_int
+    lib.gp_workspace_bytes.argtypes = [vp]
+    lib.gp_workspace_bytes.restype = i64
     lib.gp_profile_enable.argtypes = [vp, i32]
     lib.gp_profile_enable.restype = ctypes.c_int
     lib.gp_profile_read.argtypes = [vp, ctypes.POINTER(ProfRow), i32, i32]
@@ -255,6 +259,15 @@ class Graph:
         st = _lib.gp_set_stream(self._h, stream)
         if st != OK:
             raise GPError(st, "gp_set_stream")
+
+    def set_workspace_limit(self, nbytes: int):
+        """Most device bytes the handle's buffers may grow to (-1: no limit)."""
+        st = _lib.gp_set_workspace_limit(self._h, int(nbytes))
+        if st != OK:
+            raise GPError(st, "gp_set_workspace_limit")
+
+    def workspace_bytes(self) -> int:
+        return int(_lib.gp_workspace_bytes(self._h))
 
     def partition(self, opts: Options | None = None, part=None, trace_cap: int = 0):
         """Returns (part, Result[, trace]) - part is int8[n]: 0 = CPU, 1 = GPU."""

@@ -23,6 +23,20 @@ using namespace gpk;
 
 namespace {
 
+// Device bytes a handle holds in its buffers and the most it may hold (-1:
+// no limit).  A call on a handle charges every buffer it grows or frees to
+// the handle's budget through tl_ws, set for the call's duration by WsScope.
+struct WsBudget {
+  int64_t cap = -1;
+  int64_t used = 0;
+};
+thread_local WsBudget* tl_ws = nullptr;
+struct WsScope {
+  WsBudget* prev;
+  explicit WsScope(WsBudget* b) : prev(tl_ws) { tl_ws = b; }
+  ~WsScope() { tl_ws = prev; }
+};
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
@@ -30,19 +44,24 @@ struct DBuf {
   bool ensure(size_t n) {
     if (n == 0) n = 1;
     if (p && n <= cap) return true;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
+    // refuse before freeing, so a refused call leaves the buffer as it was
+    const int64_t grow = (int64_t)((n - cap) * sizeof(T));
+    if (tl_ws && tl_ws->cap >= 0 && tl_ws->used + grow > tl_ws->cap) return false;
+    release();
     if (hipMalloc((void**)&p, n * sizeof(T)) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       return false;
     }
     cap = n;
+    if (tl_ws) tl_ws->used += (int64_t)(n * sizeof(T));
     return true;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      if (tl_ws) tl_ws->used -= (int64_t)(cap * sizeof(T));
+    }
     p = nullptr;
     cap = 0;
   }
@@ -86,6 +105,8 @@ uint64_t host_mix64(uint64_t z) {
 struct gp_graph {
   hipStream_t stream = nullptr;
   int flags = 0;
+  WsBudget ws;              // this handle's buffers
+  WsBudget* wsp = &ws;      // the budget they are charged to (a k-way parent's for its subgraphs)
   int32_t n = 0;
   int64_t nnz = 0;
   int64_t sum[2] = {0, 0};
@@ -358,17 +379,33 @@ gp_status gp_set_stream(gp_graph* g, void* stream) {
 void gp_destroy(gp_graph* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
+  WsScope ws(g->wsp);
   delete g;
 }
 
-gp_status gp_create(gp_graph** out, int32_t n, const int32_t* xadj, const int32_t* adjncy,
-                    const int64_t* adjwgt, const int64_t* vwgt, int32_t flags, void* stream) {
+gp_status gp_set_workspace_limit(gp_graph* g, int64_t bytes) {
+  if (!g || bytes < -1) return GP_EINVAL;
+  g->ws.cap = bytes;
+  return GP_OK;
+}
+
+int64_t gp_workspace_bytes(const gp_graph* g) { return g ? g->ws.used : -1; }
+
+}  // extern "C"
+
+// gp_create with its buffers charged to budget (the new handle's own when
+// null); a k-way partition charges its subgraphs to the parent handle
+static gp_status create_graph(gp_graph** out, int32_t n, const int32_t* xadj,
+                              const int32_t* adjncy, const int64_t* adjwgt, const int64_t* vwgt,
+                              int32_t flags, void* stream, WsBudget* budget) {
   if (!out) return GP_EINVAL;
   *out = nullptr;
   if (n < 0) return GP_EINVAL;
   if (n > 0 && (!xadj || !vwgt)) return GP_EINVAL;
   gp_graph* g = new (std::nothrow) gp_graph();
   if (!g) return GP_ENOMEM;
+  if (budget) g->wsp = budget;
+  WsScope ws(g->wsp);
   g->stream = (hipStream_t)stream;
   g->flags = flags;
   g->n = n;
@@ -475,12 +512,21 @@ gp_status gp_create(gp_graph** out, int32_t n, const int32_t* xadj, const int32_
   return GP_OK;
 }
 
+extern "C" gp_status gp_create(gp_graph** out, int32_t n, const int32_t* xadj,
+                               const int32_t* adjncy, const int64_t* adjwgt, const int64_t* vwgt,
+                               int32_t flags, void* stream) {
+  return create_graph(out, n, xadj, adjncy, adjwgt, vwgt, flags, stream, nullptr);
+}
+
+extern "C" {
+
 static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* part,
                                      gp_result* res, int64_t* trace, int32_t trace_cap);
 
 static gp_status run_partition(gp_graph* g, const gp_options* o, int8_t* part, gp_result* res,
                                int64_t* trace, int32_t trace_cap) {
   if (g && g->profiling) g_prof = &g->prof;
+  WsScope ws(g ? g->wsp : tl_ws);
   gp_status st = run_partition_inner(g, o, part, res, trace, trace_cap);
   if (g && g->profiling) {
     (void)hipStreamSynchronize(g->stream);
@@ -495,6 +541,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
   if (!g || !res || (g->n > 0 && !part)) return GP_EINVAL;
   gp_status st = check_options(o);
   if (st != GP_OK) return st;
+  g->last_levels = -1;  // the levels are rebuilt; none is readable until the run completes
   const int32_t n = g->n;
   const int bal = o->balance_on;
   gp_result r;
@@ -712,6 +759,7 @@ gp_status gp_model_scores(const void* model, gp_graph* g, float* scores) {
   const MpModel* m = (const MpModel*)model;
   if (!g || !m || m->magic != kMpMagic || (g->n > 0 && !scores)) return GP_EINVAL;
   if (g->n == 0) return GP_OK;
+  WsScope ws(g->wsp);
   Level* l0 = g->lv[0];
   const size_t nh = (size_t)g->n * kMpH;
   if (!g->m_ha.ensure(nh) || !g->m_hb.ensure(nh) || !g->m_inv.ensure(g->n) ||
@@ -802,6 +850,7 @@ gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const 
     return GP_OK;
   }
   hipStream_t s = g->stream;
+  WsScope ws(g->wsp);
   Level* l0 = g->lv[0];
   const int ntiles = (n + 1023) / 1024;
   if (!g->kw_label.ensure(n) || !g->kw_keep.ensure(n) || !g->kw_newid.ensure(n) ||
@@ -835,8 +884,8 @@ gp_status gp_partition_kway(gp_graph* g, int32_t k, const int64_t* ratio, const 
                              g->kw_svwgt.p, s));
     if (r0 + r1 > 0) {
       gp_graph* sub = nullptr;
-      st = gp_create(&sub, (int32_t)tot[0], g->kw_sxadj.p, g->kw_sadj.p, g->kw_sw.p,
-                     g->kw_svwgt.p, 0, s);
+      st = create_graph(&sub, (int32_t)tot[0], g->kw_sxadj.p, g->kw_sadj.p, g->kw_sw.p,
+                        g->kw_svwgt.p, 0, s, g->wsp);
       if (st != GP_OK) return st;
       o2.ratio[0] = r0;
       o2.ratio[1] = r1;
