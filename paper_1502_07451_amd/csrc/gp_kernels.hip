@@ -290,7 +290,7 @@ __global__ __launch_bounds__(BS) void k_init_trials(LevelView lv, const int64_t*
   b_trial_pick<BS>(K, lv.n, ctrl, tctl, tpart, tres, out_part);
 }
 
-template <int BS>
+template <int BS, bool kLongRows>
 __global__ __launch_bounds__(BS) void k_init_trials_lds(LevelView lv, const int64_t* tot, int K,
                                                         int gs, int npass, Ctrl* ctrl,
                                                         RefCtl* tctl, int8_t* tpart,
@@ -298,8 +298,8 @@ __global__ __launch_bounds__(BS) void k_init_trials_lds(LevelView lv, const int6
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   __shared__ SelShared sel;
   __shared__ RefCtl srf;
-  b_trial_lds<BS>(lv, tot, K, (int)blockIdx.x, gs, npass, ctrl, tctl, tpart, tres, dyn_lds, &sel,
-                  &srf);
+  b_trial_lds<BS, kLongRows>(lv, tot, K, (int)blockIdx.x, gs, npass, ctrl, tctl, tpart, tres,
+                             dyn_lds, &sel, &srf);
   if (!last_block(&ctrl->ctr_init, gridDim.x)) return;
   b_trial_pick<BS>(K, lv.n, ctrl, tctl, tpart, tres, out_part);
 }
@@ -762,14 +762,22 @@ bool launch_init(const LevelView& lv, int K, int gs, int npass, Ctrl* ctrl, cons
   ProfScope ps(PK_INIT_TRIALS, 0, lv.n <= kTrialLdsMax ? trial_bytes : 0.0, s);
   if (lv.n <= kTrialLdsMax) {
     const size_t dyn = trial_lds_bytes(lv.n, kTrialBlock);
-    // more than 64 KB of dynamic LDS must be allowed once (thread-safe static)
+    const int max_dyn = (int)trial_lds_bytes(kTrialLdsMax, kTrialBlock);
+    // more than 64 KB of dynamic LDS must be allowed once (thread-safe statics)
     static const bool lds_attr =
-        hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)trial_lds_bytes(kTrialLdsMax, kTrialBlock)) == hipSuccess;
+        hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) == hipSuccess &&
+        hipFuncSetAttribute((const void*)k_init_trials_lds<kTrialBlock, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn) == hipSuccess;
     if (!lds_attr) return false;
-    k_init_trials_lds<kTrialBlock><<<K, kTrialBlock, dyn, s>>>(lv, is.tot, K, gs, npass, ctrl,
-                                                               is.ctl, is.part, is.res, out_part);
+    // rows longer than two entries per lane on average: the form that reads
+    // the pick's row with the whole block (both forms give the same result)
+    if (lv.nnz > (int64_t)kTrialLongDeg * lv.n)
+      k_init_trials_lds<kTrialBlock, true><<<K, kTrialBlock, dyn, s>>>(
+          lv, is.tot, K, gs, npass, ctrl, is.ctl, is.part, is.res, out_part);
+    else
+      k_init_trials_lds<kTrialBlock, false><<<K, kTrialBlock, dyn, s>>>(
+          lv, is.tot, K, gs, npass, ctrl, is.ctl, is.part, is.res, out_part);
     KCHECK();
     return true;
   }

@@ -1905,6 +1905,7 @@ __device__ void b_trial_global(LevelView lv, const int64_t* tot, int K, int t, i
 // yields the same integers as recomputing ext - int from scratch.
 constexpr int kTrialBlock = 256;
 constexpr int kTrialLdsMax = 3072;
+constexpr int kTrialLongDeg = 128;  // mean row length above which picks read rows block-wide
 
 // gain, b (int64), xadj (int32, n + 1), side, adjacency, move flag (int8),
 // plus one dirty flag per thread of the block
@@ -1988,28 +1989,39 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
         if (e == lv.xadj[v]) s_mv[v] = 0;
       }
     }
-    // otherwise (a long queue): U row entries per thread in flight, one
-    // moved vertex per thread
-    for (int32_t v = threadIdx.x; v < n && nchunk > kChunkCap; v += BS)
-      if (s_mv[v]) {
-        constexpr int U = 8;
-        const int32_t e1 = lv.xadj[v + 1];
-        for (int32_t e = lv.xadj[v]; e < e1; e += U) {
-          int32_t y[U];
-          int64_t w[U];
+    // otherwise (a long queue): wave k takes the moved vertices among ids
+    // [64 j, 64 j + 64) for j = k mod (BS / 64) and walks each of their rows
+    // with all 64 lanes, U entries per lane in flight (long rows of dense
+    // coarse graphs cost a few round trips each, not one per U entries)
+    if (nchunk > kChunkCap) {
+      constexpr int U = 8;
+      for (int32_t b0 = (int32_t)(threadIdx.x & ~63u); b0 < n; b0 += BS) {
+        const int32_t v = b0 + lane_id();
+        const bool mine = v < n && s_mv[v] != 0;
+        uint64_t m = __ballot(mine);
+        while (m) {
+          const int32_t u = b0 + __builtin_ctzll(m);
+          m &= m - 1;
+          const int32_t e1 = lv.xadj[u + 1];
+          for (int32_t e = lv.xadj[u] + lane_id(); e < e1; e += 64 * U) {
+            int32_t y[U];
+            int64_t w[U];
 #pragma unroll
-          for (int u = 0; u < U; u++) {
-            y[u] = e + u < e1 ? lv.adj[e + u] : 0;
-            w[u] = e + u < e1 ? lv.w[e + u] : 0;
+            for (int k = 0; k < U; k++) {
+              const int32_t q = e + 64 * k;
+              y[k] = q < e1 ? lv.adj[q] : 0;
+              w[k] = q < e1 ? lv.w[q] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++)
+              if (e + 64 * k < e1)
+                atomicAdd((unsigned long long*)&s_gain[y[k]],
+                          (unsigned long long)(s_part[y[k]] == d ? -2 * w[k] : 2 * w[k]));
           }
-#pragma unroll
-          for (int u = 0; u < U; u++)
-            if (e + u < e1)
-              atomicAdd((unsigned long long*)&s_gain[y[u]],
-                        (unsigned long long)(s_part[y[u]] == d ? -2 * w[u] : 2 * w[u]));
         }
-        s_mv[v] = 0;
+        if (mine) s_mv[v] = 0;
       }
+    }
     int64_t unused_min = 0, unused_max = 0;
     block_sum_sum_min_max<BS>(mb, mn, unused_min, unused_max, sm4);
     if (threadIdx.x == 0) finish_pass(&srf, mb, mb, mn);
@@ -2020,7 +2032,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
 // Trial t of K on an LDS-resident copy of the coarsest graph; writes its
 // cut, infeasibility, loads and assignment to tres / tctl / tpart.
 // lds: trial_lds_bytes(n) bytes; sel, srf: block-shared scratch.
-template <int BS>
+template <int BS, bool kLongRows = false>
 __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int gs, int npass,
                             const Ctrl* ctrl, RefCtl* tctl, int8_t* tpart, int64_t* tres,
                             unsigned char* lds, SelShared* selp, RefCtl* srfp) {
@@ -2130,11 +2142,10 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     bool first = true;
     const bool seed_fits = s_b[seedv] <= mg;  // the first pick is the seed when it fits
     const int seed_wave = (seedv % BS) / 64;
-    constexpr int kPre = 2;                    // row entries per lane fetched ahead
     uint64_t seen = 0;     // the best as of its last fit check
     int64_t seen_b = 0;    // and that vertex's balance weight
-    while (pg < tg) {
-      const int64_t room = mg - pg;
+    // this thread's best fitting key after the last update (raises folded in)
+    auto own_best = [&](int64_t room) {
       uint64_t bk = s_best[threadIdx.x];
       const uint64_t rz = s_raise[threadIdx.x];
       if (rz) {
@@ -2155,46 +2166,28 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
         }
       }
       s_best[threadIdx.x] = bk;
-      uint64_t wk = bk;
       butterfly<64>([&](auto o) {
-        const uint64_t k2 = xor_lane<decltype(o)::value>(wk);
-        wk = k2 > wk ? k2 : wk;
+        const uint64_t k2 = xor_lane<decltype(o)::value>(bk);
+        bk = k2 > bk ? k2 : bk;
       });
-      // The pick is always one wave's best (or, first, the seed), so each
-      // wave fetches the row of its own candidate now and the global latency
-      // runs under the barrier; the wave whose candidate is picked applies
-      // the update from registers.  Candidates of different waves are
-      // different vertices (every vertex has one owner thread).
-      const int wave = (int)threadIdx.x / 64;
-      const int32_t pre = (first && seed_fits && wave == seed_wave) ? seedv : (wk ? vid(wk) : -1);
-      int32_t p0 = 0, p1 = 0;
-      int32_t py[kPre];
-      int64_t pw[kPre];
-      if (pre >= 0) {
-        p0 = s_xadj[pre];
-        p1 = s_xadj[pre + 1];
-#pragma unroll
-        for (int j = 0; j < kPre; j++) {
-          const int32_t e = p0 + lane_id() + 64 * j;
-          py[j] = e < p1 ? lv.adj[e] : 0;
-          pw[j] = e < p1 ? lv.w[e] : 0;
-        }
-      }
-      if (lane_id() == 0) s_wmax[wave] = wk;
-      __syncthreads();
+      return bk;  // the wave's best
+    };
+    // the block's pick from the waves' bests (after the barrier that
+    // publishes them); -1 when nothing fits
+    auto block_pick = [&]() {
       uint64_t gk = s_wmax[0];
 #pragma unroll
       for (int w = 1; w < BS / 64; w++) gk = s_wmax[w] > gk ? s_wmax[w] : gk;
       int32_t pick = gk ? vid(gk) : -1;
       if (first && seed_fits) pick = seedv;
       first = false;
-      if (pick < 0) break;
-      const int64_t bp = s_b[pick];
-      const int64_t room_next = room - bp;
-      // the pick's owner gets a new best from 16 lanes of the next wave (one
-      // slot each, then a 16-lane maximum), in parallel with the update,
-      // which runs in the owner's wave; a key read before the update raised
-      // it reaches s_raise as well
+      return pick;
+    };
+    // the pick's owner gets a new best from 16 lanes of the next wave (one
+    // slot each, then a 16-lane maximum), in parallel with the update; a key
+    // read before the update raised it reaches s_raise as well
+    auto rescan_owner = [&](int32_t pick, int64_t room_next) {
+      const int wave = (int)threadIdx.x / 64;
       const int own = pick % BS;
       static_assert(kTrialLdsMax <= 16 * BS, "one rescanning lane per slot");
       if (wave == ((own + 64) % BS) / 64 && lane_id() < 16) {
@@ -2208,46 +2201,120 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
         k = team_max<16>(k);
         if (lane_id() == 0) s_best[own] = k;
       }
-      auto apply = [&](int32_t y, int64_t w) {
-        const uint64_t ky = s_key[y];
-        const bool side = (ky >> 63) != 0;
-        const uint64_t nk = (ky + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
-        s_key[y] = nk;
-        if (!side && s_b[y] <= room_next) atomicMax((unsigned long long*)&s_raise[y % BS], nk);
-      };
-      if (pre == pick) {
-        // lane 0 moves the pick itself while the lanes update its neighbours
-        // (never the pick: no self loops); every LDS read is issued before
-        // any write, so the update is one round trip
-        uint64_t ky[kPre];
-        int64_t by[kPre];
+    };
+    // the pick changes side: its gain field negated, the adjacency bit kept
+    auto move_pick = [&](int32_t pick, uint64_t kp) {
+      s_part[pick] = (int8_t)gs;
+      const int64_t f = (int64_t)((kp & cField) >> 12);  // gain + 2^49
+      s_key[pick] =
+          cSide | (kp & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) | (kp & 4095);
+    };
+    // neighbour y of the pick: key updated, raise offered to its owner
+    auto raise = [&](int32_t y, uint64_t ky, int64_t by, int64_t w, int64_t room_next) {
+      const bool side = (ky >> 63) != 0;
+      const uint64_t nk = (ky + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
+      s_key[y] = nk;
+      if (!side && by <= room_next) atomicMax((unsigned long long*)&s_raise[y % BS], nk);
+    };
+    if constexpr (kLongRows) {
+      // Long rows (dense coarsest graphs): after the pick is known, the whole
+      // block reads its row, U entries per thread in flight, and updates the
+      // neighbours; one row read per pick instead of one per wave.
+      constexpr int U = 8;
+      while (pg < tg) {
+        const int64_t room = mg - pg;
+        const uint64_t wk = own_best(room);
+        if (lane_id() == 0) s_wmax[threadIdx.x / 64] = wk;
+        __syncthreads();
+        const int32_t pick = block_pick();
+        if (pick < 0) break;
+        const int64_t bp = s_b[pick];
+        const int64_t room_next = room - bp;
+        rescan_owner(pick, room_next);
+        const int32_t p0 = s_xadj[pick], p1 = s_xadj[pick + 1];
+        if (threadIdx.x == 0) move_pick(pick, s_key[pick]);
+        for (int32_t e = p0 + (int32_t)threadIdx.x; e < p1; e += BS * U) {
+          int32_t y[U];
+          int64_t w[U];
 #pragma unroll
-        for (int j = 0; j < kPre; j++) {
-          const bool act = p0 + lane_id() + 64 * j < p1;
-          ky[j] = act ? s_key[py[j]] : 0;
-          by[j] = act ? s_b[py[j]] : 0;
-        }
-        const uint64_t kp = lane_id() == 0 ? s_key[pick] : 0;
+          for (int k = 0; k < U; k++) {
+            const int32_t q = e + BS * k;
+            y[k] = q < p1 ? lv.adj[q] : 0;
+            w[k] = q < p1 ? lv.w[q] : 0;
+          }
+          uint64_t ky[U];
+          int64_t by[U];
 #pragma unroll
-        for (int j = 0; j < kPre; j++) {
-          if (p0 + lane_id() + 64 * j >= p1) continue;
-          const bool side = (ky[j] >> 63) != 0;
-          const int64_t w = pw[j];
-          const uint64_t nk = (ky[j] + ((uint64_t)(side ? -2 * w : 2 * w) << 12)) | cAdj;
-          s_key[py[j]] = nk;
-          if (!side && by[j] <= room_next)
-            atomicMax((unsigned long long*)&s_raise[py[j] % BS], nk);
+          for (int k = 0; k < U; k++) {
+            const bool act = e + BS * k < p1;
+            ky[k] = act ? s_key[y[k]] : 0;
+            by[k] = act ? s_b[y[k]] : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < U; k++)
+            if (e + BS * k < p1) raise(y[k], ky[k], by[k], w[k], room_next);
         }
-        if (lane_id() == 0) {
-          s_part[pick] = (int8_t)gs;
-          const int64_t f = (int64_t)((kp & cField) >> 12);  // gain + 2^49
-          s_key[pick] = cSide | (kp & cAdj) | ((uint64_t)(2 * (int64_t)cBias - f) << 12) |
-                        (kp & 4095);
-        }
-        for (int32_t e = p0 + lane_id() + 64 * kPre; e < p1; e += 64) apply(lv.adj[e], lv.w[e]);
+        pg += bp;
+        __syncthreads();
       }
-      pg += bp;
-      __syncthreads();
+    } else {
+      constexpr int kPre = 2;  // row entries per lane fetched ahead
+      while (pg < tg) {
+        const int64_t room = mg - pg;
+        const uint64_t wk = own_best(room);
+        // The pick is always one wave's best (or, first, the seed), so each
+        // wave fetches the row of its own candidate now and the global
+        // latency runs under the barrier; the wave whose candidate is picked
+        // applies the update from registers.  Candidates of different waves
+        // are different vertices (every vertex has one owner thread).
+        const int wave = (int)threadIdx.x / 64;
+        const int32_t pre =
+            (first && seed_fits && wave == seed_wave) ? seedv : (wk ? vid(wk) : -1);
+        int32_t p0 = 0, p1 = 0;
+        int32_t py[kPre];
+        int64_t pw[kPre];
+        if (pre >= 0) {
+          p0 = s_xadj[pre];
+          p1 = s_xadj[pre + 1];
+#pragma unroll
+          for (int j = 0; j < kPre; j++) {
+            const int32_t e = p0 + lane_id() + 64 * j;
+            py[j] = e < p1 ? lv.adj[e] : 0;
+            pw[j] = e < p1 ? lv.w[e] : 0;
+          }
+        }
+        if (lane_id() == 0) s_wmax[wave] = wk;
+        __syncthreads();
+        const int32_t pick = block_pick();
+        if (pick < 0) break;
+        const int64_t bp = s_b[pick];
+        const int64_t room_next = room - bp;
+        rescan_owner(pick, room_next);
+        if (pre == pick) {
+          // lane 0 moves the pick itself while the lanes update its
+          // neighbours (never the pick: no self loops); every LDS read is
+          // issued before any write, so the update is one round trip
+          uint64_t ky[kPre];
+          int64_t by[kPre];
+#pragma unroll
+          for (int j = 0; j < kPre; j++) {
+            const bool act = p0 + lane_id() + 64 * j < p1;
+            ky[j] = act ? s_key[py[j]] : 0;
+            by[j] = act ? s_b[py[j]] : 0;
+          }
+          const uint64_t kp = lane_id() == 0 ? s_key[pick] : 0;
+#pragma unroll
+          for (int j = 0; j < kPre; j++)
+            if (p0 + lane_id() + 64 * j < p1) raise(py[j], ky[j], by[j], pw[j], room_next);
+          if (lane_id() == 0) move_pick(pick, kp);
+          for (int32_t e = p0 + lane_id() + 64 * kPre; e < p1; e += 64) {
+            const int32_t y = lv.adj[e];
+            raise(y, s_key[y], s_b[y], lv.w[e], room_next);
+          }
+        }
+        pg += bp;
+        __syncthreads();
+      }
     }
     __syncthreads();
     for (int32_t v = threadIdx.x; v < n; v += BS) {

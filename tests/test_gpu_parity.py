@@ -395,6 +395,25 @@ def test_long_rows_one_wave_each(gp):
     assert_same(*run_both(gp, g, coarsen_to=64, ratio=(1, 3)))
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_dense_coarsest_block_rows(gp, seed):
+    """Coarsest graphs whose rows hold more than 128 entries on average: the
+    trial form that reads each pick's row with the whole block, on the input
+    itself (coarsen_to above n) and on a coarsened dense graph."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(400, 3072))
+    g = dense_random(n, int(rng.integers(300, min(n, 2000))), 900 + seed, f"dense{n}")
+    assert g.nnz > 128 * g.n
+    kw = dict(coarsen_to=4096, ratio=(1, int(rng.integers(1, 6))),
+              eps_ppm=int(rng.choice([0, 30000, 100000])), init_trials=int(rng.choice([1, 16])),
+              balance_on=seed % 2)
+    assert_same(*run_both(gp, g, **kw))
+    if seed < 2:
+        g = dense_random(12000, 700, 950 + seed, "dense12000")
+        check_hierarchy(gp, g, coarsen_to=2048, ratio=(1, 3))
+        assert_same(*run_both(gp, g, coarsen_to=2048, ratio=(1, 3)))
+
+
 def test_long_rows_beyond_packed_ids(gp):
     """Long coarse rows on a level with more than 2^19 - 1 coarse vertices,
     where the packed key does not fit: rows beyond one wave's LDS sort take
