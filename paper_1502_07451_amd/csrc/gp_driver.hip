@@ -235,7 +235,7 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
   for (int i = 0; i < g->prof.nrec; i++) {
     ProfRec& r = g->prof.recs[i];
     if (r.level != level) continue;
-    if (coarsening && (r.kind == PK_MATCH_ROUND || r.kind == PK_MATCH_SETTLE))
+    if (coarsening && (r.kind == PK_MATCH_ROUND || r.kind == PK_MATCH_FREE))
       r.executed = (r.idx <= 1 || h.made[r.idx - 1] > 0) ? 1 : 0;
     if (coarsening) {
       // the split of the coarse rows between the row kernels is known only
@@ -588,7 +588,9 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     g->prof.level = L;
     g->prof.idx = 0;
     // the long-row list is free during matching: it is the second proposal buffer
-    LCHK(launch_match_rounds(fv, f->match.p, sc.prop, sc.longlist, g->ctrl, R, hs, tw, s));
+    // the level's part array is free until the uncoarsening: the free flags
+    LCHK(launch_match_rounds(fv, f->match.p, (uint8_t*)f->part.p, sc.prop, sc.longlist, g->ctrl,
+                             R, hs, tw, s));
     LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));

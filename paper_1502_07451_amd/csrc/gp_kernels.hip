@@ -1,8 +1,9 @@
 // gp_kernels.hip - gfx950 kernels of the single-graph path and their launchers.
 //
 // Per level of the multilevel hierarchy:
-//   matching    k_match_round (R rounds, each settling the previous one),
-//               k_match_settle, k_hub, k_twohop, k_iso_count / k_iso_list /
+//   matching    k_match_round (R rounds; from the second on, k_match_free
+//               settles the previous one first), k_match_settle, k_hub,
+//               k_twohop, k_iso_count / k_iso_list /
 //               k_iso_pair
 //   contraction k_contract_count -> k_contract_map -> k_contract_rows
 //               -> k_contract_long (one wave per row) -> k_contract_huge
@@ -35,11 +36,18 @@ __global__ void k_level_reset(Ctrl* ctrl, int promote) {
 
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_match_round(LevelView lv, int32_t* match,
+                                                        const uint8_t* fr,
                                                         const int32_t* prop_prev,
                                                         int32_t* prop_cur, Ctrl* ctrl,
                                                         int round, uint64_t hs) {
-  b_match_round<TW>(lv, match, prop_prev, prop_cur, ctrl, round, hs, (int)blockIdx.x,
+  b_match_round<TW>(lv, match, fr, prop_prev, prop_cur, ctrl, round, hs, (int)blockIdx.x,
                     (int)gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_match_free(int32_t n, int32_t* match,
+                                                       const int32_t* prop_prev, uint8_t* fr,
+                                                       Ctrl* ctrl, int round) {
+  b_match_free(n, match, prop_prev, fr, ctrl, round, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_match_settle(int32_t n, int32_t* match,
@@ -341,7 +349,8 @@ __global__ void k_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_
 
 // ================================================================ profiling
 const char* const kProfNames[PK_N] = {
-    "k_match_round", "k_match_settle", "k_hub", "k_twohop", "k_iso", "k_contract_count",
+    "k_match_round", "k_match_free", "k_match_settle", "k_hub", "k_twohop", "k_iso",
+    "k_contract_count",
     "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_huge",
     "k_contract_compact", "k_init_tot",
     "k_init_trials", "k_refine_gain", "k_refine_scan", "k_refine_delta", "k_refine_settle",
@@ -419,27 +428,34 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s) {
 }
 
 template <int TW>
-static void rounds_tw(const LevelView& lv, int32_t* match, int32_t* pa, int32_t* pb,
-                      Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
+static void rounds_tw(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* pa,
+                      int32_t* pb, Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * TW, kBlock);
+  const int fgrid = grid_for(lv.n, kBlock);
   const double n = lv.n, m2 = lv.nnz;
   for (int r = 0; r < R; r++) {
     int32_t* cur = (r & 1) ? pb : pa;
     const int32_t* prev = (r & 1) ? pa : pb;
+    if (g_prof) g_prof->idx = r;
+    if (r > 0) {
+      ProfScope ps(PK_MATCH_FREE, 0, 0.0, s);
+      k_match_free<<<fgrid, kBlock, 0, s>>>(lv.n, match, prev, fr, ctrl, r);
+    }
     ProfScope ps(PK_MATCH_ROUND, TW, r == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
-    k_match_round<TW><<<grid, kBlock, 0, s>>>(lv, match, prev, cur, ctrl, r, hs);
+    k_match_round<TW><<<grid, kBlock, 0, s>>>(lv, match, fr, prev, cur, ctrl, r, hs);
   }
 }
 
-bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
-                         Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s) {
+bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* prop_a,
+                         int32_t* prop_b, Ctrl* ctrl, int R, uint64_t hs, int tw,
+                         hipStream_t s) {
   if (R <= 0) return true;
   switch (tw) {
-    case 4: rounds_tw<4>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 8: rounds_tw<8>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 16: rounds_tw<16>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 32: rounds_tw<32>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
-    default: rounds_tw<64>(lv, match, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 4: rounds_tw<4>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 8: rounds_tw<8>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 16: rounds_tw<16>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 32: rounds_tw<32>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
+    default: rounds_tw<64>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
   }
   KCHECK();
   {

@@ -37,7 +37,7 @@ int team_width_for(int32_t n, int64_t nnz);
 
 // ---- per-launch profiling (HIP events), enabled by the driver for one call
 enum ProfKind {
-  PK_MATCH_ROUND, PK_MATCH_SETTLE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
+  PK_MATCH_ROUND, PK_MATCH_FREE, PK_MATCH_SETTLE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
   PK_CONTRACT_MAP, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_HUGE, PK_CONTRACT_COMPACT,
   PK_INIT_TOT,
   PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_SCAN, PK_REFINE_DELTA, PK_REFINE_SETTLE,
@@ -71,10 +71,12 @@ struct ProfScope {
 };
 
 bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s);
-// R matching rounds, each settling the previous one, then the last settled;
-// prop_a / prop_b: two int32[n] proposal buffers
-bool launch_match_rounds(const LevelView& lv, int32_t* match, int32_t* prop_a, int32_t* prop_b,
-                         Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s);
+// R matching rounds (from the second on, a settle of the previous round that
+// marks the free vertices in fr, then the proposals), then the last settled;
+// fr: uint8[n] scratch; prop_a / prop_b: two int32[n] proposal buffers
+bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* prop_a,
+                         int32_t* prop_b, Ctrl* ctrl, int R, uint64_t hs, int tw,
+                         hipStream_t s);
 bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratch& sc,
                    uint64_t hs, int tw, hipStream_t s);
 bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t* vc,

@@ -126,28 +126,46 @@ __device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
   if (threadIdx.x == 0 && made) atomicAdd(&ctrl->made[round], made);
 }
 
-// One matching round that also settles the previous one (single-graph
-// path): round r's kernel first makes the mutual proposals of round r-1
-// final for its own vertex, then proposes among the neighbours that are
-// still free.  A neighbour v is free when match[v] is -1 and v's round r-1
-// proposal was not mutual; v's own thread may be storing the settled value
-// at the same time, but both reads give the same answer.  Proposals are
+// Matching rounds of the single-graph path.  Round r >= 1 runs in two
+// kernels: b_match_free settles the mutual proposals of round r - 1 and
+// marks the vertices still free (fr[v] = 1 when match[v] is -1 afterwards),
+// then b_match_round proposes among the free neighbours, so the test of a
+// neighbour is one byte gathered from an n-byte array.  Proposals are
 // double-buffered (prop_prev, prop_cur), and b_match_settle settles the last
 // round.  Rounds after one that matched nothing repeat its proposals and
 // match nothing, so running them all yields the same matching as stopping.
+//
+// When settling round r - 1 matched nothing, round r proposes exactly what
+// round r - 1 did (same free vertices, same rule), so it has no mutual pair
+// either and every later round repeats it: those rounds return at once.
+// Both proposal buffers then hold the same proposals, so the final settle
+// reads either.  made[r] = 1 records that round r's settle matched.
+__device__ __forceinline__ void b_match_free(int32_t n, int32_t* match, const int32_t* prop_prev,
+                                             uint8_t* fr, Ctrl* ctrl, int round, int bid_,
+                                             int nblk_) {
+  if (round >= 2 && ctrl->made[round - 1] == 0) return;
+  bool settled = false;
+  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
+       u += (int64_t)nblk_ * kBlock) {
+    int32_t m = match[u];
+    const int32_t p = prop_prev[u];
+    if (m == -1 && p >= 0 && prop_prev[p] == (int32_t)u) {
+      m = p;
+      match[u] = p;
+      settled = true;
+    }
+    fr[u] = m == -1 ? 1 : 0;
+  }
+  if (__syncthreads_or(settled) && threadIdx.x == 0) ctrl->made[round] = 1;
+}
+
 template <int TW>
-__device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
+__device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match, const uint8_t* fr,
                                               const int32_t* prop_prev, int32_t* prop_cur,
                                               Ctrl* ctrl, int round, uint64_t hs,
                                               int bid_, int nblk_) {
-  // When settling round r - 1 matched nothing, round r proposed exactly what
-  // round r - 1 did (same free vertices, same rule), so it has no mutual
-  // pair either and every later round repeats it: those rounds return at
-  // once.  Both proposal buffers then hold the same proposals, so the final
-  // settle reads either.  made[r] = 1 records that round r's settle matched.
   if (round >= 2 && ctrl->made[round - 1] == 0) return;
   const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
-  bool settled = false;
   const int lane = threadIdx.x & (TW - 1);
   const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
@@ -157,37 +175,23 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
     // any test, so that each chain costs as few global round trips as it can
     const int64_t bu = lv.b[u];
     const int32_t e0 = lv.xadj[u], e1 = lv.xadj[u + 1];
-    int32_t mu = -1;
     if (round > 0) {
-      mu = match[u];
-      const int32_t p = prop_prev[u];
-      if (mu == -1 && p >= 0 && prop_prev[p] == u) {
-        mu = p;
-        settled = true;
-        if (lane == 0) match[u] = p;
+      const bool free_u = fr[u] != 0;
+      const int32_t t = prop_prev[u];
+      if (!free_u) {
+        if (lane == 0) prop_cur[u] = -1;
+        continue;
       }
-    } else if (lane == 0) {
-      match[u] = -1;
-    }
-    if (mu != -1) {
-      if (lane == 0) prop_cur[u] = -1;
-      continue;
-    }
-    if (round > 0) {
       // The neighbours free at this round's start are a subset of those free
       // at the previous round's start, and the weight cap does not change:
       // if u's previous choice t is still free, t is still the best, and if
       // u had no choice it still has none.  Only the others rescan the row.
-      const int32_t t = prop_prev[u];
-      bool keep = t < 0;
-      if (!keep) {
-        const int32_t mt = match[t], pt = prop_prev[t];
-        keep = mt == -1 && !(pt >= 0 && prop_prev[pt] == t);
-      }
-      if (keep) {
+      if (t < 0 || fr[t] != 0) {
         if (lane == 0) prop_cur[u] = t;
         continue;
       }
+    } else if (lane == 0) {
+      match[u] = -1;
     }
     const bool capcheck = bu + maxb > cap;
     int64_t bw = -1;
@@ -196,12 +200,7 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
       const int32_t v = lv.adj[e];
       const int64_t w = lv.w[e];
       const int64_t bv_v = capcheck ? lv.b[v] : 0;
-      if (round > 0) {
-        const int32_t mv = match[v];
-        const int32_t pv = prop_prev[v];
-        if (mv != -1) continue;
-        if (pv >= 0 && prop_prev[pv] == v) continue;
-      }
+      if (round > 0 && fr[v] == 0) continue;
       if (capcheck && bu + bv_v > cap) continue;
       if (match_better(w, v, bw, bv, hs, u)) {
         bw = w;
@@ -218,7 +217,6 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match,
     });
     if (lane == 0) prop_cur[u] = bv;
   }
-  if (round >= 1 && __syncthreads_or(settled) && threadIdx.x == 0) ctrl->made[round] = 1;
 }
 
 // settles the mutual proposals of the last round
