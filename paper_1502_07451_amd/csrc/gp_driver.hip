@@ -588,9 +588,14 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     g->prof.level = L;
     g->prof.idx = 0;
     // the long-row list is free during matching: it is the second proposal buffer
-    // the level's part array is free until the uncoarsening: the free flags
-    LCHK(launch_match_rounds(fv, f->match.p, (uint8_t*)f->part.p, sc.prop, sc.longlist, g->ctrl,
-                             R, hs, tw, s));
+    // the level's part array is free until the uncoarsening (the free
+    // flags), the contraction's member lists and the reduction partials
+    // until the contraction (the free lists and their lengths)
+    static_assert(5 * 4096 * sizeof(int64_t) >= 2 * kMatchSegMax * sizeof(int32_t),
+                  "partials hold both list-length arrays");
+    LCHK(launch_match_rounds(fv, f->match.p, (uint8_t*)f->part.p, sc.cmem0, sc.cmem1,
+                             (int32_t*)sc.partials, sc.prop, sc.longlist, g->ctrl, R, hs, tw,
+                             s));
     LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));

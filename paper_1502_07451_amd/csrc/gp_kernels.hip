@@ -34,20 +34,25 @@ __global__ void k_level_reset(Ctrl* ctrl, int promote) {
   b_level_reset(ctrl, promote, (int)blockIdx.x, (int)gridDim.x);
 }
 
+// one block per segment of the vertex range (see b_match_free)
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_match_round(LevelView lv, int32_t* match,
-                                                        const uint8_t* fr,
+                                                        const uint8_t* fr, const int32_t* list,
+                                                        const int32_t* lcnt,
                                                         const int32_t* prop_prev,
                                                         int32_t* prop_cur, Ctrl* ctrl,
                                                         int round, uint64_t hs) {
-  b_match_round<TW>(lv, match, fr, prop_prev, prop_cur, ctrl, round, hs, (int)blockIdx.x,
-                    (int)gridDim.x);
+  b_match_round<TW>(lv, match, fr, list, lcnt, prop_prev, prop_cur, ctrl, round, hs,
+                    (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_match_free(int32_t n, int32_t* match,
                                                        const int32_t* prop_prev, uint8_t* fr,
-                                                       Ctrl* ctrl, int round) {
-  b_match_free(n, match, prop_prev, fr, ctrl, round, (int)blockIdx.x, (int)gridDim.x);
+                                                       const int32_t* lin, const int32_t* cin,
+                                                       int32_t* lout, int32_t* cout, Ctrl* ctrl,
+                                                       int round) {
+  b_match_free(n, match, prop_prev, fr, lin, cin, lout, cout, ctrl, round, (int)blockIdx.x,
+               (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_match_settle(int32_t n, int32_t* match,
@@ -428,10 +433,11 @@ bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s) {
 }
 
 template <int TW>
-static void rounds_tw(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* pa,
-                      int32_t* pb, Ctrl* ctrl, int R, uint64_t hs, hipStream_t s) {
-  const int grid = grid_for((int64_t)lv.n * TW, kBlock);
-  const int fgrid = grid_for(lv.n, kBlock);
+static void rounds_tw(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* const* lists,
+                      int32_t* const* cnts, int32_t* pa, int32_t* pb, Ctrl* ctrl, int R,
+                      uint64_t hs, hipStream_t s) {
+  // segments: as many blocks as the rows' teams fill, the same for both kernels
+  const int nseg = grid_for((int64_t)lv.n * TW, kBlock, kMatchSegMax);
   const double n = lv.n, m2 = lv.nnz;
   for (int r = 0; r < R; r++) {
     int32_t* cur = (r & 1) ? pb : pa;
@@ -439,23 +445,28 @@ static void rounds_tw(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t*
     if (g_prof) g_prof->idx = r;
     if (r > 0) {
       ProfScope ps(PK_MATCH_FREE, 0, 0.0, s);
-      k_match_free<<<fgrid, kBlock, 0, s>>>(lv.n, match, prev, fr, ctrl, r);
+      k_match_free<<<nseg, kBlock, 0, s>>>(lv.n, match, prev, fr, lists[(r - 1) & 1],
+                                           cnts[(r - 1) & 1], lists[r & 1], cnts[r & 1], ctrl,
+                                           r);
     }
     ProfScope ps(PK_MATCH_ROUND, TW, r == 0 ? 4 * (n + 1) + 12 * m2 + 12 * n : 0.0, s);
-    k_match_round<TW><<<grid, kBlock, 0, s>>>(lv, match, fr, prev, cur, ctrl, r, hs);
+    k_match_round<TW><<<nseg, kBlock, 0, s>>>(lv, match, fr, lists[r & 1], cnts[r & 1], prev,
+                                              cur, ctrl, r, hs);
   }
 }
 
-bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* prop_a,
-                         int32_t* prop_b, Ctrl* ctrl, int R, uint64_t hs, int tw,
-                         hipStream_t s) {
+bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* list_a,
+                         int32_t* list_b, int32_t* seg_cnt, int32_t* prop_a, int32_t* prop_b,
+                         Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s) {
   if (R <= 0) return true;
+  int32_t* const lists[2] = {list_a, list_b};
+  int32_t* const cnts[2] = {seg_cnt, seg_cnt + kMatchSegMax};
   switch (tw) {
-    case 4: rounds_tw<4>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 8: rounds_tw<8>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 16: rounds_tw<16>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
-    case 32: rounds_tw<32>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
-    default: rounds_tw<64>(lv, match, fr, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 4: rounds_tw<4>(lv, match, fr, lists, cnts, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 8: rounds_tw<8>(lv, match, fr, lists, cnts, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 16: rounds_tw<16>(lv, match, fr, lists, cnts, prop_a, prop_b, ctrl, R, hs, s); break;
+    case 32: rounds_tw<32>(lv, match, fr, lists, cnts, prop_a, prop_b, ctrl, R, hs, s); break;
+    default: rounds_tw<64>(lv, match, fr, lists, cnts, prop_a, prop_b, ctrl, R, hs, s); break;
   }
   KCHECK();
   {

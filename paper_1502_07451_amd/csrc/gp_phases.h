@@ -128,64 +128,87 @@ __device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
 
 // Matching rounds of the single-graph path.  Round r >= 1 runs in two
 // kernels: b_match_free settles the mutual proposals of round r - 1 and
-// marks the vertices still free (fr[v] = 1 when match[v] is -1 afterwards),
-// then b_match_round proposes among the free neighbours, so the test of a
-// neighbour is one byte gathered from an n-byte array.  Proposals are
-// double-buffered (prop_prev, prop_cur), and b_match_settle settles the last
-// round.  Rounds after one that matched nothing repeat its proposals and
-// match nothing, so running them all yields the same matching as stopping.
+// lists the vertices still free (fr[v] = 1 when match[v] is -1 afterwards),
+// then b_match_round proposes for the listed vertices only, among their free
+// neighbours, so the test of a neighbour is one byte gathered from an
+// n-byte array and a late round costs what its few free vertices cost.
+// Both kernels run one block per segment: segment k is vertex range
+// [kS, kS + S) (S = ceil(n / blocks)); its list of round r holds the free
+// vertices of that range in ascending id at slots [kS, kS + cnt[k]), so no
+// global counter is needed.  Round r's settle only visits list r - 1 (round
+// 0: every vertex), since a vertex matched before stays matched.  Proposals
+// are double-buffered (prop_prev, prop_cur); an entry of a vertex that is no
+// longer listed goes stale, which no one reads: a listed vertex proposes to
+// a listed one.  b_match_settle settles the last round.
 //
 // When settling round r - 1 matched nothing, round r proposes exactly what
 // round r - 1 did (same free vertices, same rule), so it has no mutual pair
 // either and every later round repeats it: those rounds return at once.
-// Both proposal buffers then hold the same proposals, so the final settle
-// reads either.  made[r] = 1 records that round r's settle matched.
+// Both proposal buffers then hold the same proposals of the listed
+// vertices, so the final settle reads either.  made[r] = 1 records that
+// round r's settle matched.
 __device__ __forceinline__ void b_match_free(int32_t n, int32_t* match, const int32_t* prop_prev,
-                                             uint8_t* fr, Ctrl* ctrl, int round, int bid_,
-                                             int nblk_) {
+                                             uint8_t* fr, const int32_t* lin,
+                                             const int32_t* cin, int32_t* lout, int32_t* cout,
+                                             Ctrl* ctrl, int round, int seg, int nseg) {
   if (round >= 2 && ctrl->made[round - 1] == 0) return;
+  __shared__ int32_t smi[kBlock / 64];
+  const int64_t S = ((int64_t)n + nseg - 1) / nseg;
+  const int64_t lo = (int64_t)seg * S;
+  const int64_t hi = lo + S < n ? lo + S : n;
+  const int32_t cnt = round == 1 ? (int32_t)(hi > lo ? hi - lo : 0) : cin[seg];
   bool settled = false;
-  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
-       u += (int64_t)nblk_ * kBlock) {
-    int32_t m = match[u];
-    const int32_t p = prop_prev[u];
-    if (m == -1 && p >= 0 && prop_prev[p] == (int32_t)u) {
-      m = p;
-      match[u] = p;
-      settled = true;
+  int32_t kept = 0;
+  for (int32_t i0 = 0; i0 < cnt; i0 += kBlock) {
+    const int32_t i = i0 + (int32_t)threadIdx.x;
+    bool keep = false;
+    int32_t u = 0;
+    if (i < cnt) {
+      u = round == 1 ? (int32_t)(lo + i) : lin[lo + i];
+      int32_t m = match[u];
+      const int32_t p = prop_prev[u];
+      if (m == -1 && p >= 0 && prop_prev[p] == u) {
+        m = p;
+        match[u] = p;
+        settled = true;
+      }
+      keep = m == -1;
+      fr[u] = keep ? 1 : 0;
     }
-    fr[u] = m == -1 ? 1 : 0;
+    int32_t tot;
+    const int32_t ex = block_exscan<kBlock, int32_t>(keep ? 1 : 0, smi, &tot);
+    if (keep) lout[lo + kept + ex] = u;
+    kept += tot;
   }
+  if (threadIdx.x == 0) cout[seg] = kept;
   if (__syncthreads_or(settled) && threadIdx.x == 0) ctrl->made[round] = 1;
 }
 
 template <int TW>
 __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match, const uint8_t* fr,
+                                              const int32_t* list, const int32_t* lcnt,
                                               const int32_t* prop_prev, int32_t* prop_cur,
-                                              Ctrl* ctrl, int round, uint64_t hs,
-                                              int bid_, int nblk_) {
+                                              Ctrl* ctrl, int round, uint64_t hs, int seg,
+                                              int nseg) {
   if (round >= 2 && ctrl->made[round - 1] == 0) return;
   const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
   const int lane = threadIdx.x & (TW - 1);
-  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
-  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
-  for (int64_t uu = team; uu < lv.n; uu += nteams) {
-    const int32_t u = (int32_t)uu;
+  const int64_t S = ((int64_t)lv.n + nseg - 1) / nseg;
+  const int64_t lo = (int64_t)seg * S;
+  const int64_t hi = lo + S < lv.n ? lo + S : lv.n;
+  const int32_t cnt = round == 0 ? (int32_t)(hi > lo ? hi - lo : 0) : lcnt[seg];
+  for (int32_t ii = (int32_t)threadIdx.x / TW; ii < cnt; ii += kBlock / TW) {
+    const int32_t u = round == 0 ? (int32_t)(lo + ii) : list[lo + ii];
     // loads that do not depend on each other are issued together, before
     // any test, so that each chain costs as few global round trips as it can
     const int64_t bu = lv.b[u];
     const int32_t e0 = lv.xadj[u], e1 = lv.xadj[u + 1];
     if (round > 0) {
-      const bool free_u = fr[u] != 0;
-      const int32_t t = prop_prev[u];
-      if (!free_u) {
-        if (lane == 0) prop_cur[u] = -1;
-        continue;
-      }
       // The neighbours free at this round's start are a subset of those free
       // at the previous round's start, and the weight cap does not change:
       // if u's previous choice t is still free, t is still the best, and if
       // u had no choice it still has none.  Only the others rescan the row.
+      const int32_t t = prop_prev[u];
       if (t < 0 || fr[t] != 0) {
         if (lane == 0) prop_cur[u] = t;
         continue;
@@ -196,15 +219,34 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match, cons
     const bool capcheck = bu + maxb > cap;
     int64_t bw = -1;
     int32_t bv = -1;
-    for (int32_t e = e0 + lane; e < e1; e += TW) {
-      const int32_t v = lv.adj[e];
-      const int64_t w = lv.w[e];
-      const int64_t bv_v = capcheck ? lv.b[v] : 0;
-      if (round > 0 && fr[v] == 0) continue;
-      if (capcheck && bu + bv_v > cap) continue;
-      if (match_better(w, v, bw, bv, hs, u)) {
-        bw = w;
-        bv = v;
+    // U entries per lane in flight on long rows (wide teams): the entry
+    // loads, then the gathers they feed, then the tests (the maximum does not
+    // depend on the order); short rows keep one, for fewer registers
+    constexpr int U = TW >= 32 ? 4 : (TW == 16 ? 2 : 1);
+    for (int32_t e = e0 + lane; e < e1; e += TW * U) {
+      int32_t vk[U];
+      int64_t wk[U];
+#pragma unroll
+      for (int k = 0; k < U; k++) {
+        const int32_t q = e + TW * k;
+        vk[k] = q < e1 ? lv.adj[q] : 0;
+        wk[k] = q < e1 ? lv.w[q] : 0;
+      }
+      bool ok[U];
+      int64_t bk[U];
+#pragma unroll
+      for (int k = 0; k < U; k++) {
+        const bool in = e + TW * k < e1;
+        ok[k] = in && (round == 0 || fr[vk[k]] != 0);
+        bk[k] = in && capcheck ? lv.b[vk[k]] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < U; k++) {
+        if (!ok[k] || (capcheck && bu + bk[k] > cap)) continue;
+        if (match_better(wk[k], vk[k], bw, bv, hs, u)) {
+          bw = wk[k];
+          bv = vk[k];
+        }
       }
     }
     butterfly<TW>([&](auto o) {
