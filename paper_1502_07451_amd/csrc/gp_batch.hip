@@ -314,6 +314,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.n = f.n;
     fv.nnz = f.nnz;
     fv.xadj = f.xadj;
+    fv.xend = f.xadj + 1;
     fv.adj = f.adj;
     fv.w = f.w;
     fv.b = a.bal ? f.vg : f.vc;
@@ -392,6 +393,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     cv.n = cl.n;
     cv.nnz = cl.nnz;
     cv.xadj = cl.xadj;
+    cv.xend = cl.xadj + 1;
     cv.adj = cl.adj;
     cv.w = cl.w;
     cv.b = a.bal ? cl.vg : cl.vc;
@@ -458,6 +460,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.n = f.n;
     fv.nnz = f.nnz;
     fv.xadj = f.xadj;
+    fv.xend = f.xadj + 1;
     fv.adj = f.adj;
     fv.w = f.w;
     fv.b = a.bal ? f.vg : f.vc;
@@ -475,6 +478,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   v0w.n = l0.n;
   v0w.nnz = l0.nnz;
   v0w.xadj = l0.xadj;
+  v0w.xend = l0.xadj + 1;
   v0w.adj = l0.adj;
   v0w.w = l0.w;
   v0w.b = a.bal ? l0.vg : l0.vc;

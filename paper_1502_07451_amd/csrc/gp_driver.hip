@@ -69,17 +69,19 @@ struct DBuf {
 
 struct Level {
   int32_t n = 0;
-  int64_t nnz = 0;
-  DBuf<int32_t> xadj, adj, match, cmap;
+  int64_t nnz = 0;   // entries
+  bool gapped = false;  // rows at their upper-bound offsets: xe holds the row ends
+  int64_t span = 0;     // with gaps: the extent of adj / w in use
+  DBuf<int32_t> xadj, xe, adj, match, cmap;
   DBuf<int64_t> w, vc, vg;
   DBuf<int8_t> part;
   bool ensure(int64_t ncap, int64_t nnzcap) {
-    return xadj.ensure(ncap + 1) && adj.ensure(nnzcap) && w.ensure(nnzcap) &&
+    return xadj.ensure(ncap + 1) && xe.ensure(ncap) && adj.ensure(nnzcap) && w.ensure(nnzcap) &&
            vc.ensure(ncap) && vg.ensure(ncap) && match.ensure(ncap) && cmap.ensure(ncap) &&
            part.ensure(ncap);
   }
   void release() {
-    xadj.release(); adj.release(); match.release(); cmap.release();
+    xadj.release(); xe.release(); adj.release(); match.release(); cmap.release();
     w.release(); vc.release(); vg.release(); part.release();
   }
   LevelView view(int bal) const {
@@ -87,6 +89,7 @@ struct Level {
     v.n = n;
     v.nnz = (int32_t)nnz;
     v.xadj = xadj.p;
+    v.xend = gapped ? xe.p : xadj.p + 1;
     v.adj = adj.p;
     v.w = w.p;
     v.b = bal ? vg.p : vc.p;
@@ -599,17 +602,26 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));
-    LCHK(launch_contract_b(fv, f->cmap.p, g->ctrl, sc, f->n, c->xadj.p, c->adj.p, c->w.p, s));
+    LCHK(launch_contract_b(fv, f->cmap.p, g->ctrl, sc, f->n, c->xadj.p, c->xe.p, c->adj.p,
+                           c->w.p, s));
     if ((st = read_ctrl(g)) != GP_OK) return st;
     prof_mark(g, L, true);
     c->n = h.nc;
     c->nnz = h.nnz_c;
+    c->gapped = true;
+    c->span = h.ubtot;
     pairs[L] = (int64_t)f->n - c->n;
     L++;
     if (20 * (int64_t)c->n > 19 * (int64_t)f->n || L == kMaxLevels) break;
   }
-  // coarsest level: greedy-growing trials
+  // coarsest level: made compact (the trials keep its n + 1 offsets in LDS),
+  // then the greedy-growing trials
   Level* cl = g->lv[L];
+  if (cl->gapped) {
+    LCHK(launch_compact_level(g->ctrl, sc, cl->n, (int32_t)cl->nnz, cl->xadj.p, cl->adj.p,
+                              cl->w.p, s));
+    cl->gapped = false;
+  }
   const bool learned = (o->flags & GP_LEARNED) && cl->n > 0 && cl->n <= kMpMaxN;
   {
     const int K = o->init_trials < cl->n ? o->init_trials : cl->n;
@@ -814,9 +826,33 @@ gp_status gp_level_read(gp_graph* g, int32_t level, int32_t* n, int64_t* nnz, in
   if (nnz) *nnz = l->nnz;
   hipStream_t s = g->stream;
   const size_t nv = (size_t)l->n, ne = (size_t)l->nnz;
-  if (xadj) HIPCHK(hipMemcpyAsync(xadj, l->xadj.p, 4 * (nv + 1), hipMemcpyDeviceToHost, s));
-  if (adjncy && ne) HIPCHK(hipMemcpyAsync(adjncy, l->adj.p, 4 * ne, hipMemcpyDeviceToHost, s));
-  if (adjwgt && ne) HIPCHK(hipMemcpyAsync(adjwgt, l->w.p, 8 * ne, hipMemcpyDeviceToHost, s));
+  if (l->gapped && nv > 0 && (xadj || adjncy || adjwgt)) {
+    // rows at their upper-bound offsets: gathered into compact form here
+    std::vector<int32_t> b(nv), e(nv), ka((size_t)l->span);
+    std::vector<int64_t> wa((size_t)l->span);
+    HIPCHK(hipMemcpyAsync(b.data(), l->xadj.p, 4 * nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(e.data(), l->xe.p, 4 * nv, hipMemcpyDeviceToHost, s));
+    if (l->span > 0) {
+      HIPCHK(hipMemcpyAsync(ka.data(), l->adj.p, 4 * (size_t)l->span, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(wa.data(), l->w.p, 8 * (size_t)l->span, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    size_t o = 0;
+    for (size_t v = 0; v < nv; v++) {
+      if (xadj) xadj[v] = (int32_t)o;
+      for (int32_t q = b[v]; q < e[v]; q++, o++) {
+        if (adjncy) adjncy[o] = ka[q];
+        if (adjwgt) adjwgt[o] = wa[q];
+      }
+    }
+    if (xadj) xadj[nv] = (int32_t)o;
+  } else {
+    if (xadj) HIPCHK(hipMemcpyAsync(xadj, l->xadj.p, 4 * (nv + 1), hipMemcpyDeviceToHost, s));
+    if (adjncy && ne)
+      HIPCHK(hipMemcpyAsync(adjncy, l->adj.p, 4 * ne, hipMemcpyDeviceToHost, s));
+    if (adjwgt && ne)
+      HIPCHK(hipMemcpyAsync(adjwgt, l->w.p, 8 * ne, hipMemcpyDeviceToHost, s));
+  }
   if (vwgt && nv) {
     HIPCHK(hipMemcpy2DAsync(vwgt, 16, l->vc.p, 8, 8, nv, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpy2DAsync(vwgt + 1, 16, l->vg.p, 8, 8, nv, hipMemcpyDeviceToHost, s));

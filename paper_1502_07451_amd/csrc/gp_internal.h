@@ -100,13 +100,18 @@ enum : uint32_t {
   kVInval = 1u, kVRange = 2u, kVSelf = 4u, kVDup = 8u, kVAsym = 16u, kVOverflow = 32u
 };
 
-// device view of one level
+// device view of one level.  Row u is adj / w [xadj[u], xend[u]).  A level
+// built by the single-graph contraction keeps each row where its upper bound
+// put it, so rows may have gaps between them; a compact level (the input
+// graph, the coarsest level, every level of the batched path) has
+// xend = xadj + 1.  nnz counts the entries, not the span.
 struct LevelView {
   int32_t n, nnz;
   const int32_t* xadj;
   const int32_t* adj;
   const int64_t* w;
   const int64_t* b;     // balance column
+  const int32_t* xend;
 };
 
 }  // namespace gpk

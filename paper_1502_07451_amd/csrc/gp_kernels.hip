@@ -7,7 +7,9 @@
 //               k_iso_pair
 //   contraction k_contract_count -> k_contract_map -> k_contract_rows
 //               -> k_contract_long (one wave per row) -> k_contract_huge
-//               (one block per row) -> k_contract_compact
+//               (one block per row) -> k_contract_ends; rows stay at their
+//               upper-bound offsets, and only the coarsest level is made
+//               compact (k_tile_scan -> k_contract_compact)
 // at the coarsest level
 //   initial bisection k_init_tot -> k_init_trials_lds (one trial per block)
 // per level on the way back up
@@ -157,6 +159,26 @@ __global__ __launch_bounds__(kBlock) void k_contract_huge(LevelView lv, const in
 
 __global__ __launch_bounds__(kBlock) void k_tile_scan(Ctrl* ctrl, int64_t* tile_cnt, int ntiles_c) {
   b_tile_scan(ctrl, tile_cnt, ntiles_c);
+}
+
+// Begin and end of every coarse row (a row stays where its upper-bound
+// offset put it) and the level's entry count.
+__global__ __launch_bounds__(kBlock) void k_contract_ends(Ctrl* ctrl, const int64_t* toff,
+                                                          const int32_t* cnt, int32_t* cxadj,
+                                                          int32_t* cxend) {
+  __shared__ int64_t sml[kBlock / 64];
+  const int32_t nc = ctrl->nc;
+  int64_t sum = 0;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc;
+       c += (int64_t)gridDim.x * kBlock) {
+    const int32_t b = (int32_t)toff[c], k = cnt[c];
+    cxadj[c] = b;
+    cxend[c] = b + k;
+    sum += k;
+  }
+  sum = block_sum<kBlock, int64_t>(sum, sml);
+  if (threadIdx.x == 0 && sum) atomicAdd(&ctrl->nnz_c, (int32_t)sum);
+  if (blockIdx.x == 0 && threadIdx.x == 0) cxadj[nc] = (int32_t)ctrl->ubtot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_contract_compact(const Ctrl* ctrl,
@@ -545,19 +567,20 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
   return true;
 }
 
-// nc_max: an upper bound of the coarse vertex count (sizes the grids)
+// nc_max: an upper bound of the coarse vertex count (sizes the grids).  The
+// coarse rows are written straight into cadj / cw at their upper-bound
+// offsets; cxadj / cxend get their begins and ends.
 bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, const Scratch& sc,
-                       int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
-                       hipStream_t s) {
+                       int32_t nc_max, int32_t* cxadj, int32_t* cxend, int32_t* cadj,
+                       int64_t* cw, hipStream_t s) {
   const int ntc = (nc_max + kTileC - 1) / kTileC;
   const int ntc1 = ntc > 0 ? ntc : 1;
-  const int g = grid_for(ntc1, 1, 4096);
   {
     // algorithmic bytes are set after the level (they depend on the long rows)
     ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
     k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(
-        lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt, sc.tile_cnt,
-        sc.longlist, ctrl, ntc1, sc.prop);
+        lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw, sc.cnt, sc.tile_cnt, sc.longlist,
+        ctrl, ntc1, sc.prop);
   }
   KCHECK();
   {
@@ -567,8 +590,8 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     // every coarse row may be long: up to one wave per row, at most the ten
     // waves per compute unit that the LDS holds
     const int gw = nc_max < 2560 ? (nc_max > 0 ? nc_max : 1) : 2560;
-    k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk,
-                                      sc.tmpv, sc.cnt, sc.tile_cnt, sc.longlist);
+    k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,
+                                      sc.cnt, sc.tile_cnt, sc.longlist);
   }
   KCHECK();
   // the dense window plus a staged copy of one row (96 KB)
@@ -583,19 +606,37 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     // their list), one block each
     // up to one block per row; one block per compute unit fits the LDS
     const int glong = nc_max < 512 ? (nc_max > 0 ? nc_max : 1) : 512;
-    k_contract_huge<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl,
-                                               sc.tmpk, sc.tmpv, sc.cnt, sc.tile_cnt, sc.prop,
-                                               ntc1);
+    k_contract_huge<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
+                                               cw, sc.cnt, sc.tile_cnt, sc.prop, ntc1);
   }
   KCHECK();
+  k_contract_ends<<<grid_for(nc_max, kBlock), kBlock, 0, s>>>(ctrl, sc.toff, sc.cnt, cxadj,
+                                                               cxend);
+  KCHECK();
+  return true;
+}
+
+// The coarse level just built by launch_contract_b, made compact: the
+// per-tile entry counts are scanned, the rows are copied in order to
+// tmpk / tmpv and back, and cxadj gets the n + 1 exact offsets.
+bool launch_compact_level(Ctrl* ctrl, const Scratch& sc, int32_t nc, int32_t nnz,
+                          int32_t* cxadj, int32_t* cadj, int64_t* cw, hipStream_t s) {
+  const int ntc = (nc + kTileC - 1) / kTileC;
+  const int ntc1 = ntc > 0 ? ntc : 1;
   k_tile_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_cnt, ntc1);
   KCHECK();
   {
-    ProfScope ps(PK_CONTRACT_COMPACT, 0, 0.0, s);
-    k_contract_compact<<<g, kBlock, 0, s>>>(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv,
-                                            cxadj, cadj, cw, ntc1);
+    ProfScope ps(PK_CONTRACT_COMPACT, 0, 24.0 * nnz + 16.0 * nc, s);
+    k_contract_compact<<<grid_for(ntc1, 1, 4096), kBlock, 0, s>>>(
+        ctrl, sc.toff, sc.cnt, sc.tile_cnt, cadj, cw, cxadj, sc.tmpk, sc.tmpv, ntc1);
   }
   KCHECK();
+  if (nnz > 0 &&
+      (hipMemcpyAsync(cadj, sc.tmpk, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice,
+                      s) != hipSuccess ||
+       hipMemcpyAsync(cw, sc.tmpv, sizeof(int64_t) * (size_t)nnz, hipMemcpyDeviceToDevice,
+                      s) != hipSuccess))
+    return false;
   return true;
 }
 

@@ -85,8 +85,11 @@ bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t*
                        const int64_t* vg, Ctrl* ctrl, const Scratch& sc, int32_t* cmap,
                        int64_t* cvc, int64_t* cvg, hipStream_t s);
 bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, const Scratch& sc,
-                       int32_t nc_max, int32_t* cxadj, int32_t* cadj, int64_t* cw,
-                       hipStream_t s);
+                       int32_t nc_max, int32_t* cxadj, int32_t* cxend, int32_t* cadj,
+                       int64_t* cw, hipStream_t s);
+// makes the level built by the last launch_contract_b compact (nnz entries)
+bool launch_compact_level(Ctrl* ctrl, const Scratch& sc, int32_t nc, int32_t nnz,
+                          int32_t* cxadj, int32_t* cadj, int64_t* cw, hipStream_t s);
 // per-vertex state of the passes of one level, sized for level 0
 struct RefArrays {
   int64_t* ext;   // n: weight to the other side, kept up to date across passes

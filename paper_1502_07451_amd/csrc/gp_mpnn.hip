@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_input(LevelView lv, const int64_t
   const int64_t wv = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
   const int64_t nw = (int64_t)gridDim.x * kBlock / 64;
   for (int64_t v = wv; v < lv.n; v += nw) {
-    const int32_t e0 = lv.xadj[v], e1 = lv.xadj[v + 1];
+    const int32_t e0 = lv.xadj[v], e1 = lv.xend[v];
     int64_t tw = 0;
     for (int32_t q = e0 + lane; q < e1; q += 64) tw += lv.w[q];
     tw = team_sum<64>(tw);
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_layer(LevelView lv, const uint16_
   const int64_t nw = (int64_t)gridDim.x * kBlock / 64;
   for (int64_t v = wv; v < lv.n; v += nw) {
     float acc = 0.0f;
-    for (int32_t q = lv.xadj[v]; q < lv.xadj[v + 1]; q++) {
+    for (int32_t q = lv.xadj[v]; q < lv.xend[v]; q++) {
       const float e = mp_phi(lv.w[q]) / 64.0f;
       acc = __builtin_fmaf(e, bf2f(hin[(int64_t)lv.adj[q] * kMpH + lane]), acc);
     }
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_propose(LevelView lv, const float
     int64_t g = 0;
     const int8_t pv = s_part[v];
     constexpr int U = 8;  // row entries in flight per thread
-    const int32_t e1 = lv.xadj[v + 1];
+    const int32_t e1 = lv.xend[v];
     for (int32_t e = lv.xadj[v]; e < e1; e += U) {
       int32_t y[U];
       int64_t w[U];

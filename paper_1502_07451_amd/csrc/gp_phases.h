@@ -78,7 +78,7 @@ __device__ __forceinline__ void b_match_propose(LevelView lv, const int32_t* mat
     const bool capcheck = bu + maxb > cap;
     int64_t bw = -1;
     int32_t bv = -1;
-    const int32_t e1 = lv.xadj[u + 1];
+    const int32_t e1 = lv.xend[u];
     for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
       const int32_t v = lv.adj[e];
       if (round > 0 && match[v] != -1) continue;
@@ -202,7 +202,7 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match, cons
     // loads that do not depend on each other are issued together, before
     // any test, so that each chain costs as few global round trips as it can
     const int64_t bu = lv.b[u];
-    const int32_t e0 = lv.xadj[u], e1 = lv.xadj[u + 1];
+    const int32_t e0 = lv.xadj[u], e1 = lv.xend[u];
     if (round > 0) {
       // The neighbours free at this round's start are a subset of those free
       // at the previous round's start, and the weight cap does not change:
@@ -289,7 +289,7 @@ __device__ __forceinline__ void b_hub(LevelView lv, const int32_t* match, int32_
     }
     int64_t bw = -1;
     int32_t bv = -1;
-    const int32_t e1 = lv.xadj[u + 1];
+    const int32_t e1 = lv.xend[u];
     for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
       const int32_t v = lv.adj[e];
       const int64_t w = lv.w[e];
@@ -326,7 +326,7 @@ __device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub,
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
   for (int64_t hh = team; hh < lv.n; hh += nteams) {
     const int32_t h = (int32_t)hh;
-    const int32_t e1 = lv.xadj[h + 1];
+    const int32_t e1 = lv.xend[h];
     int32_t pending = -1;
     for (int32_t e0 = lv.xadj[h]; e0 < e1; e0 += TW) {
       const int32_t e = e0 + lane;
@@ -384,7 +384,7 @@ __device__ __forceinline__ void b_iso_count(LevelView lv, const int32_t* match,
     const int64_t base = (int64_t)t * kTileV + threadIdx.x * 4;
     for (int j = 0; j < 4; j++) {
       const int64_t u = base + j;
-      if (u < lv.n && match[u] == -1 && lv.xadj[u + 1] == lv.xadj[u]) c++;
+      if (u < lv.n && match[u] == -1 && lv.xend[u] == lv.xadj[u]) c++;
     }
     c = block_sum<kBlock, int32_t>(c, smi);
     if (threadIdx.x == 0) tile_cnt[t] = c;
@@ -404,7 +404,7 @@ __device__ __forceinline__ void b_iso_list(LevelView lv, const int32_t* match,
     int32_t c = 0;
     for (int j = 0; j < 4; j++) {
       const int64_t u = base + j;
-      f[j] = u < lv.n && match[u] == -1 && lv.xadj[u + 1] == lv.xadj[u];
+      f[j] = u < lv.n && match[u] == -1 && lv.xend[u] == lv.xadj[u];
       c += f[j];
     }
     int32_t tot;
@@ -451,10 +451,10 @@ __device__ __forceinline__ void b_contract_count(LevelView lv, const int32_t* ma
       const int32_t m = match[u];
       if (m < 0 || u < m) {
         lead++;
-        ub += lv.xadj[u + 1] - lv.xadj[u];
+        ub += lv.xend[u] - lv.xadj[u];
         int64_t bsum = lv.b[u];
         if (m >= 0) {
-          ub += lv.xadj[m + 1] - lv.xadj[m];
+          ub += lv.xend[m] - lv.xadj[m];
           bsum += lv.b[m];
         }
         mx = bsum > mx ? bsum : mx;
@@ -540,8 +540,8 @@ __device__ __forceinline__ void b_contract_map(LevelView lv, const int32_t* matc
       mm[j] = m;
       if (m < 0 || u < m) {
         lead++;
-        ub += lv.xadj[u + 1] - lv.xadj[u];
-        if (m >= 0) ub += lv.xadj[m + 1] - lv.xadj[m];
+        ub += lv.xend[u] - lv.xadj[u];
+        if (m >= 0) ub += lv.xend[m] - lv.xadj[m];
       }
     }
     int32_t tl;
@@ -554,12 +554,12 @@ __device__ __forceinline__ void b_contract_map(LevelView lv, const int32_t* matc
       if (m == -2 || !(m < 0 || u < m)) continue;
       cmap[u] = c;
       int64_t sc = vc[u], sg = vg[u];
-      int64_t d = lv.xadj[u + 1] - lv.xadj[u];
+      int64_t d = lv.xend[u] - lv.xadj[u];
       if (m >= 0) {
         cmap[m] = c;
         sc += vc[m];
         sg += vg[m];
-        d += lv.xadj[m + 1] - lv.xadj[m];
+        d += lv.xend[m] - lv.xadj[m];
       }
       cvc[c] = sc;
       cvg[c] = sg;
@@ -609,9 +609,9 @@ __device__ __forceinline__ CoarseRowLoader coarse_loader(const LevelView& lv, co
   ld.c = c;
   const int32_t m0 = cmem0[c], m1 = cmem1[c];
   ld.e0 = lv.xadj[m0];
-  ld.d0 = lv.xadj[m0 + 1] - ld.e0;
+  ld.d0 = lv.xend[m0] - ld.e0;
   ld.e1 = m1 >= 0 ? lv.xadj[m1] : 0;
-  const int d1 = m1 >= 0 ? lv.xadj[m1 + 1] - ld.e1 : 0;
+  const int d1 = m1 >= 0 ? lv.xend[m1] - ld.e1 : 0;
   *L = ld.d0 + d1;
   return ld;
 }
@@ -670,9 +670,9 @@ __device__ __forceinline__ void b_contract_rows(
       if ((int)threadIdx.x < rows) {
         const int32_t c = c0 + (int32_t)threadIdx.x;
         const int32_t m0 = cmem0[c], m1 = cmem1[c];
-        const int32_t e0 = lv.xadj[m0], d0 = lv.xadj[m0 + 1] - e0;
+        const int32_t e0 = lv.xadj[m0], d0 = lv.xend[m0] - e0;
         const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0;
-        const int32_t d1 = m1 >= 0 ? lv.xadj[m1 + 1] - e1 : 0;
+        const int32_t d1 = m1 >= 0 ? lv.xend[m1] - e1 : 0;
         L = d0 + d1;
         s_e0[threadIdx.x] = e0;
         s_d0[threadIdx.x] = d0;
@@ -1149,7 +1149,7 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
       const int32_t v = (int32_t)uu;
       const int8_t pv = part[v];
       int64_t ext = 0, in = 0;
-      const int32_t e1 = lv.xadj[v + 1];
+      const int32_t e1 = lv.xend[v];
       int32_t e = lv.xadj[v] + lane;
       // four entries per lane in flight: their neighbour and side loads
       // overlap instead of forming one dependent chain per entry
@@ -1460,7 +1460,7 @@ __device__ __forceinline__ void b_refine_delta(LevelView lv, const int8_t* part,
     const int32_t u = list[i].v;
     if (mark[u] != stamp) continue;  // the whole team skips together
     int64_t corr = 0;
-    const int32_t e1 = lv.xadj[u + 1];
+    const int32_t e1 = lv.xend[u];
     for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
       const int32_t x = lv.adj[e];
       const int64_t w = lv.w[e];
@@ -1499,7 +1499,7 @@ __device__ __forceinline__ void b_vol_out(LevelView lv, int64_t* out, int bid_, 
   for (int64_t vv = team; vv < lv.n; vv += nteams) {
     const int32_t v = (int32_t)vv;
     int64_t m = 0;
-    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW)
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xend[v]; e += TW)
       if (lv.adj[e] > v && lv.w[e] > m) m = lv.w[e];
     m = team_max<TW, int64_t>(m);
     if (lane == 0) out[v] = m;
@@ -1517,7 +1517,7 @@ __device__ __forceinline__ void b_vol_count(LevelView lv, const int8_t* part, in
     const int32_t v = (int32_t)vv;
     const int8_t pv = part[v];
     int32_t c = 0;
-    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xend[v]; e += TW) {
       const int32_t x = lv.adj[e];
       c += x > v && part[x] != pv;
     }
@@ -1554,7 +1554,7 @@ __device__ __forceinline__ void b_vol_gain(LevelView lv, const int8_t* part, con
       const int8_t pv = part[v];
       int64_t ext = 0, pred = 0;
       int32_t succ_s = 0, succ_d = 0;
-      for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+      for (int32_t e = lv.xadj[v] + lane; e < lv.xend[v]; e += TW) {
         const int32_t x = lv.adj[e];
         const int8_t px = part[x];
         if (px != pv) ext += lv.w[e];
@@ -1616,7 +1616,7 @@ __device__ __forceinline__ void b_vol_total(LevelView lv, const int8_t* part, co
     if (vv < lv.n) {
       const int32_t v = (int32_t)vv;
       const int8_t pv = part[v];
-      for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW) {
+      for (int32_t e = lv.xadj[v] + lane; e < lv.xend[v]; e += TW) {
         const int32_t x = lv.adj[e];
         c += x > v && part[x] != pv;
       }
@@ -1643,7 +1643,7 @@ __device__ __forceinline__ void b_final_stats(LevelView lv, const int64_t* vc,
     const int32_t v = (int32_t)uu;
     const int8_t pv = part[v];
     int64_t ext = 0;
-    for (int32_t e = lv.xadj[v] + lane; e < lv.xadj[v + 1]; e += TW)
+    for (int32_t e = lv.xadj[v] + lane; e < lv.xend[v]; e += TW)
       if (part[lv.adj[e]] != pv) ext += lv.w[e];
     ext = team_sum<TW>(ext);
     if (lane == 0) {
@@ -1714,7 +1714,7 @@ __device__ __forceinline__ void b_init_tot(LevelView lv, int64_t* tot, int bid_,
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
   for (int64_t v = team; v < lv.n; v += nteams) {
     int64_t s = 0;
-    const int32_t e1 = lv.xadj[v + 1];
+    const int32_t e1 = lv.xend[v];
     for (int32_t e = lv.xadj[v] + lane; e < e1; e += TW) s += lv.w[e];
     s = team_sum<TW>(s);
     if (lane == 0) tot[v] = s;
@@ -1776,7 +1776,7 @@ __device__ void refine_block(const LevelView& lv, int8_t* part, RefCtl* rc, Cand
       if (v < lv.n) {
         const int8_t pv = part[v];
         int64_t ext = 0, in = 0;
-        for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++) {
+        for (int32_t e = lv.xadj[v]; e < lv.xend[v]; e++) {
           if (part[lv.adj[e]] != pv) ext += lv.w[e];
           else in += lv.w[e];
         }
@@ -1905,7 +1905,7 @@ __device__ void b_trial_global(LevelView lv, const int64_t* tot, int K, int t, i
     first = false;
     if (pick < 0) break;
     if (threadIdx.x == 0) part[pick] = (int8_t)gs;
-    for (int32_t e = lv.xadj[pick] + threadIdx.x; e < lv.xadj[pick + 1]; e += BS) {
+    for (int32_t e = lv.xadj[pick] + threadIdx.x; e < lv.xend[pick]; e += BS) {
       const int32_t x = lv.adj[e];
       conn[x] += lv.w[e];
       adjc[x] += 1;
@@ -1926,7 +1926,7 @@ __device__ void b_trial_global(LevelView lv, const int64_t* tot, int K, int t, i
   int64_t ext = 0;
   for (int32_t v = threadIdx.x; v < n; v += BS) {
     const int8_t pv = part[v];
-    for (int32_t e = lv.xadj[v]; e < lv.xadj[v + 1]; e++)
+    for (int32_t e = lv.xadj[v]; e < lv.xend[v]; e++)
       if (part[lv.adj[e]] != pv) ext += lv.w[e];
   }
   ext = block_sum<BS, int64_t>(ext, sml);
@@ -1998,7 +1998,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
         s_gain[v] = -c.gain;
         mb += c.b;
         mn++;
-        const int32_t a = lv.xadj[v], nc = (lv.xadj[v + 1] - a + kChunk - 1) / kChunk;
+        const int32_t a = lv.xadj[v], nc = (lv.xend[v] - a + kChunk - 1) / kChunk;
         const int slot = atomicAdd(&s_nchunk, nc);
         for (int k = 0; k < nc && slot + k < kChunkCap; k++) {
           s_chunk_v[slot + k] = v;
@@ -2013,7 +2013,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
       // all moved vertices cost about one global round trip together
       for (int c = threadIdx.x; c < nchunk; c += BS) {
         const int32_t v = s_chunk_v[c], e = s_chunk_e[c];
-        const int32_t e1 = lv.xadj[v + 1];
+        const int32_t e1 = lv.xend[v];
         int32_t y[kChunk];
         int64_t w[kChunk];
 #pragma unroll
@@ -2042,7 +2042,7 @@ __device__ void lds_refine(const LevelView& lv, int64_t* s_gain, const int64_t* 
         while (m) {
           const int32_t u = b0 + __builtin_ctzll(m);
           m &= m - 1;
-          const int32_t e1 = lv.xadj[u + 1];
+          const int32_t e1 = lv.xend[u];
           for (int32_t e = lv.xadj[u] + lane_id(); e < e1; e += 64 * U) {
             int32_t y[U];
             int64_t w[U];
@@ -2099,6 +2099,7 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
     s_mv[v] = 0;
     W += bv;
   }
+  // the coarsest level is compact: n + 1 offsets
   for (int32_t v = threadIdx.x; v <= n; v += BS) s_xadj[v] = lv.xadj[v];
   s_dirty[threadIdx.x] = 0;
   W = block_sum<BS, int64_t>(W, sml);
@@ -2525,6 +2526,7 @@ __device__ void b_trial_lds(LevelView lv, const int64_t* tot, int K, int t, int 
   __syncthreads();
   LevelView lvl = lv;
   lvl.xadj = s_xadj;
+  lvl.xend = s_xadj + 1;
   lds_refine<BS>(lvl, s_gain, s_b, s_part, s_mv, srf, sel);
   // cut = sum over v of (gain + tot) / 4
   int64_t q = 0;
