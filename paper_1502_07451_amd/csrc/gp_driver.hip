@@ -167,7 +167,8 @@ struct gp_graph {
     return prop.ensure(n1) && tile_lead.ensure(n1 / kTileV + 2) &&
            tile_ub.ensure(n1 / kTileV + 2) && cmem0.ensure(n1) && cmem1.ensure(n1) &&
            toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
-           tmpk.ensure(nnz) && tmpv.ensure(nnz) && longlist.ensure(n1) && list.ensure(n1) &&
+           tmpk.ensure(nnz > n1 ? nnz : n1) && tmpv.ensure(nnz) && longlist.ensure(n1) &&
+           list.ensure(n1) &&
            partials.ensure(5 * 4096) && r_ext.ensure(n1) && r_inn.ensure(n1) &&
            r_mark.ensure(n1);
   }

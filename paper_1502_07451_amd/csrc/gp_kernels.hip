@@ -5,7 +5,8 @@
 //               settles the previous one first), k_match_settle, k_hub,
 //               k_twohop, k_iso_count / k_iso_list /
 //               k_iso_pair
-//   contraction k_contract_count -> k_contract_map -> k_contract_rows
+//   contraction k_contract_count -> k_contract_map -> k_contract_short
+//               (rows of <= 32 candidates) -> k_contract_rows
 //               -> k_contract_long (one wave per row) -> k_contract_huge
 //               (one block per row) -> k_contract_ends; rows stay at their
 //               upper-bound offsets, and only the coarsest level is made
@@ -121,13 +122,42 @@ __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int
                  tile_cnt, ntiles_c, (int)blockIdx.x, (int)gridDim.x);
 }
 
+// one block per segment of the coarse rows (see b_contract_short)
+__global__ __launch_bounds__(kBlock) void k_contract_short(LevelView lv, const int32_t* cmap,
+                                                           const int32_t* cmem0,
+                                                           const int32_t* cmem1,
+                                                           const int64_t* toff, const Ctrl* ctrl,
+                                                           int32_t* okey, int64_t* oval,
+                                                           int32_t* cnt, int32_t* defer,
+                                                           int32_t* dcnt) {
+  b_contract_short(lv, cmap, cmem0, cmem1, toff, ctrl, okey, oval, cnt, defer, dcnt,
+                   (int)blockIdx.x, (int)gridDim.x);
+}
+
+// the rows the short-row kernel listed, block k taking segment k's, 16 at a
+// time (the same grid as k_contract_short)
 __global__ __launch_bounds__(kBlock) void k_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
     const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
-    int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, int32_t* hugelist) {
+    int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, int32_t* hugelist,
+    const int32_t* rowlist, const int32_t* rowcnt) {
   __shared__ __align__(16) unsigned char lds[kRowBlockCap * 12];
   b_contract_rows(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist, wctrl,
-                  ntiles_c, lds, (int)blockIdx.x, (int)gridDim.x, hugelist);
+                  ntiles_c, lds, (int)blockIdx.x, (int)gridDim.x, hugelist, rowlist, rowcnt);
+}
+
+// per-tile entry counts of the coarse rows (for the compaction's scan)
+__global__ __launch_bounds__(kBlock) void k_tile_count(const Ctrl* ctrl, const int32_t* cnt,
+                                                       int64_t* tile_cnt, int ntiles_c) {
+  const int32_t nc = ctrl->nc;
+  for (int t = blockIdx.x * (kBlock / 64) + threadIdx.x / 64; t < ntiles_c;
+       t += gridDim.x * (kBlock / 64)) {
+    const int32_t c = t * kTileC + lane_id();
+    static_assert(kTileC == 64, "one lane per row of a tile");
+    int64_t k = c < nc ? cnt[c] : 0;
+    k = team_sum<64, int64_t>(k);
+    if (lane_id() == 0) tile_cnt[t] = k;
+  }
 }
 
 // one wave per long row (packed-key sort in the wave's 16 KB of LDS)
@@ -578,9 +608,18 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   {
     // algorithmic bytes are set after the level (they depend on the long rows)
     ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
-    k_contract_rows<<<grid_for(nc_max, kRowsPerBlock, 16384), kBlock, 0, s>>>(
-        lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw, sc.cnt, sc.tile_cnt, sc.longlist,
-        ctrl, ntc1, sc.prop);
+    // rows of <= 32 candidates; the others are listed per segment in
+    // sc.tmpk (free here; at least n slots), with their counts in
+    // sc.partials, then sorted by the row kernel
+    static_assert(5 * 4096 * sizeof(int64_t) >= kContractSegMax * sizeof(int32_t),
+                  "partials hold the segment counts");
+    const int nseg = grid_for((int64_t)nc_max * 32, kBlock, kContractSegMax);
+    int32_t* dcnt = (int32_t*)sc.partials;
+    k_contract_short<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
+                                             cw, sc.cnt, sc.tmpk, dcnt);
+    k_contract_rows<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,
+                                            sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1, sc.prop,
+                                            sc.tmpk, dcnt);
   }
   KCHECK();
   {
@@ -623,6 +662,8 @@ bool launch_compact_level(Ctrl* ctrl, const Scratch& sc, int32_t nc, int32_t nnz
                           int32_t* cxadj, int32_t* cadj, int64_t* cw, hipStream_t s) {
   const int ntc = (nc + kTileC - 1) / kTileC;
   const int ntc1 = ntc > 0 ? ntc : 1;
+  k_tile_count<<<grid_for(ntc1, kBlock / 64), kBlock, 0, s>>>(ctrl, sc.cnt, sc.tile_cnt, ntc1);
+  KCHECK();
   k_tile_scan<<<1, kBlock, 0, s>>>(ctrl, sc.tile_cnt, ntc1);
   KCHECK();
   {

@@ -645,12 +645,13 @@ __device__ __forceinline__ void b_contract_rows(
     LevelView lv, const int32_t* cmap, const int32_t* cmem0, const int32_t* cmem1,
     const int64_t* toff, const Ctrl* ctrl, int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
     int64_t* tile_cnt, int32_t* longlist, Ctrl* wctrl, int ntiles_c, unsigned char* lds,
-    int bid_, int nblk_, int32_t* hugelist = nullptr) {
+    int bid_, int nblk_, int32_t* hugelist = nullptr, const int32_t* rowlist = nullptr,
+    const int32_t* rowcnt = nullptr) {
   // lds: kBlock/64 wave-private regions of kWaveCap x (int64 + int32) bytes
   int64_t* sv = (int64_t*)lds;
   int32_t* sk = (int32_t*)(sv + kRowBlockCap);
   constexpr int R = kRowsPerBlock;
-  __shared__ int32_t s_e0[R], s_d0[R], s_e1[R], s_len[R];
+  __shared__ int32_t s_e0[R], s_d0[R], s_e1[R], s_len[R], s_c[R];
   // rows of each register or LDS class: [0] <= 32, [1] <= 64, [2] <= kWaveCap
   __shared__ int8_t s_list[3][R];
   __shared__ int32_t s_count[3];
@@ -658,17 +659,23 @@ __device__ __forceinline__ void b_contract_rows(
   static_assert(R == kBlock / 16 && R <= 64, "a 16-lane team per row; the rows fit one wave");
   static_assert(kTileC % R == 0, "row groups nest in compaction tiles");
   (void)ntiles_c;
+  // rowlist: block k sorts the rows b_contract_short listed in its segment
+  // (rowcnt[k] of them, at rowlist[kS ...]), else every coarse row
   const int32_t nc = ctrl->nc;
+  const int64_t S = rowlist ? ((int64_t)nc + nblk_ - 1) / nblk_ : 0;
+  const int32_t nrow = rowlist ? rowcnt[bid_] : nc;
+  if (rowlist) rowlist += bid_ * S;
   const int wave = threadIdx.x / 64;
-  const int32_t ngroups = (nc + R - 1) / R;
-  for (int32_t grp = bid_; grp < ngroups; grp += nblk_) {
+  const int32_t ngroups = (nrow + R - 1) / R;
+  for (int32_t grp = rowlist ? 0 : bid_; grp < ngroups; grp += rowlist ? 1 : nblk_) {
     const int32_t c0 = grp * R;
-    const int rows = c0 + R < nc ? R : nc - c0;
+    const int rows = c0 + R < nrow ? R : nrow - c0;
     if (threadIdx.x < 64) {
       // wave 0 reads the rows' members and sorts the rows into classes
       int L = 0;
       if ((int)threadIdx.x < rows) {
-        const int32_t c = c0 + (int32_t)threadIdx.x;
+        const int32_t c = rowlist ? rowlist[c0 + threadIdx.x] : c0 + (int32_t)threadIdx.x;
+        s_c[threadIdx.x] = c;
         const int32_t m0 = cmem0[c], m1 = cmem1[c];
         const int32_t e0 = lv.xadj[m0], d0 = lv.xend[m0] - e0;
         const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0;
@@ -709,7 +716,7 @@ __device__ __forceinline__ void b_contract_rows(
       ld.adj = lv.adj;
       ld.w = lv.w;
       ld.cmap = cmap;
-      ld.c = c0 + i;
+      ld.c = s_c[i];
       ld.e0 = s_e0[i];
       ld.d0 = s_d0[i];
       ld.e1 = s_e1[i];
@@ -718,23 +725,23 @@ __device__ __forceinline__ void b_contract_rows(
     {
       const int i = (int)threadIdx.x / 16;
       if (i < rows && s_len[i] <= 16) {
-        const int32_t c = c0 + i;
+        const int32_t c = s_c[i];
         team_row<16>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
       }
     }
     for (int q = (int)threadIdx.x / 32; q < s_count[0]; q += kBlock / 32) {
       const int i = s_list[0][q];
-      const int32_t c = c0 + i;
+      const int32_t c = s_c[i];
       team_row<32>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
     }
     for (int q = wave; q < s_count[1]; q += kBlock / 64) {
       const int i = s_list[1][q];
-      const int32_t c = c0 + i;
+      const int32_t c = s_c[i];
       team_row<64>(loader(i), s_len[i], tmpk + toff[c], tmpv + toff[c], &cnt[c]);
     }
     for (int q = wave; q < s_count[2]; q += kBlock / 64) {
       const int i = s_list[2][q];
-      const int32_t c = c0 + i;
+      const int32_t c = s_c[i];
       int k;
       if (nc < kPackMaxNc) {
         // packed keys in the wave's region (kWaveCap keys)
@@ -748,13 +755,61 @@ __device__ __forceinline__ void b_contract_rows(
       if (lane_id() == 0) cnt[c] = k;
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (!rowlist && threadIdx.x < 64) {
       int64_t sum = (int)threadIdx.x < rows ? cnt[c0 + threadIdx.x] : 0;
       sum = team_sum<64, int64_t>(sum);
       if (threadIdx.x == 0 && sum)
         atomicAdd((unsigned long long*)&tile_cnt[c0 / kTileC], (unsigned long long)sum);
     }
   }
+}
+
+// Rows of at most 32 candidates, one 32-lane team each: the team reads its
+// row's members, gathers and sorts the candidates in registers and writes
+// the merged row.  Block k takes the rows [kS, kS + S) (S = ceil(nc /
+// blocks)) and lists its longer rows at defer[kS ...], dcnt[k] of them,
+// for b_contract_rows (no global counter).  With few registers and no
+// barrier in the row loop, many rows' gather chains are in flight at once on
+// the large sparse levels.
+__device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cmap,
+                                                 const int32_t* cmem0, const int32_t* cmem1,
+                                                 const int64_t* toff, const Ctrl* ctrl,
+                                                 int32_t* okey, int64_t* oval, int32_t* cnt,
+                                                 int32_t* defer, int32_t* dcnt, int seg,
+                                                 int nseg) {
+  constexpr int T = 32;
+  __shared__ int32_t s_nd;
+  if (threadIdx.x == 0) s_nd = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & (T - 1);
+  const int32_t nc = ctrl->nc;
+  const int64_t S = ((int64_t)nc + nseg - 1) / nseg;
+  const int64_t lo = (int64_t)seg * S;
+  const int64_t hi = lo + S < nc ? lo + S : nc;
+  for (int64_t cc = lo + threadIdx.x / T; cc < hi; cc += kBlock / T) {
+    const int32_t c = (int32_t)cc;
+    const int32_t m0 = cmem0[c], m1 = cmem1[c];
+    const int64_t o = toff[c];
+    const int32_t e0 = lv.xadj[m0], x0 = lv.xend[m0];
+    const int32_t e1 = m1 >= 0 ? lv.xadj[m1] : 0, x1 = m1 >= 0 ? lv.xend[m1] : 0;
+    const int L = (x0 - e0) + (x1 - e1);
+    if (L > T) {
+      if (lane == 0) defer[lo + atomicAdd(&s_nd, 1)] = c;
+      continue;
+    }
+    CoarseRowLoader ld;
+    ld.xadj = lv.xadj;
+    ld.adj = lv.adj;
+    ld.w = lv.w;
+    ld.cmap = cmap;
+    ld.c = c;
+    ld.e0 = e0;
+    ld.d0 = x0 - e0;
+    ld.e1 = e1;
+    team_row<T>(ld, L, okey + o, oval + o, &cnt[c]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) dcnt[seg] = s_nd;
 }
 
 // exclusive scan of the coarse-tile entry counts; their total is 2m of the
