@@ -248,8 +248,13 @@ static void prof_mark(gp_graph* g, int level, bool coarsening) {
       const double nf = g->lv[level]->n, mf = g->lv[level]->nnz;
       const double nc = h.nc, mc = h.nnz_c, li = (double)h.long_in, lo = (double)h.long_out;
       const double hi = (double)h.huge_in, ho = (double)h.huge_out;
+      const double si = (double)h.short_in, so = (double)h.short_out;
+      // the short-row kernel reads every row's members and offsets; the row
+      // kernel those of the rows it was left, and their list entries
+      const double nd = (double)h.deferred;
+      if (r.kind == PK_CONTRACT_SHORT) r.bytes = 16 * si + 12 * so + 8 * nf + 20 * nc;
       if (r.kind == PK_CONTRACT_ROWS)
-        r.bytes = 16 * (mf - li - hi) + 12 * (mc - lo - ho) + 8 * nf + 20 * nc;
+        r.bytes = 16 * (mf - si - li - hi) + 12 * (mc - so - lo - ho) + 40 * nd;
       if (r.kind == PK_CONTRACT_LONG) r.bytes = 16 * li + 12 * lo;
       if (r.kind == PK_CONTRACT_HUGE) r.bytes = 16 * hi + 12 * ho;
       if (r.kind == PK_CONTRACT_COMPACT) r.bytes = 24 * mc + 16 * nc + 4;

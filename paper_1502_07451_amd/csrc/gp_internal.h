@@ -78,6 +78,8 @@ struct Ctrl {
   int64_t ubtot;
   int64_t long_in, long_out;  // candidates read and entries written by the long-row kernel
   int64_t huge_in, huge_out;  // the same for the rows of one block each
+  int64_t short_in, short_out;  // the same for the rows of <= 32 candidates
+  int64_t deferred;            // rows the short-row kernel left to the row kernel
   int64_t maxb_next;
   uint32_t ctr_count, ctr_long, ctr_stats, ctr_init;
   int32_t niso;           // unmatched vertices without neighbours

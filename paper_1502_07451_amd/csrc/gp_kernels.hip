@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int
 __global__ __launch_bounds__(kBlock) void k_contract_short(LevelView lv, const int32_t* cmap,
                                                            const int32_t* cmem0,
                                                            const int32_t* cmem1,
-                                                           const int64_t* toff, const Ctrl* ctrl,
+                                                           const int64_t* toff, Ctrl* ctrl,
                                                            int32_t* okey, int64_t* oval,
                                                            int32_t* cnt, int32_t* defer,
                                                            int32_t* dcnt) {
@@ -408,7 +408,7 @@ __global__ void k_split_vwgt(int32_t n, const int64_t* vwgt, int64_t* vc, int64_
 const char* const kProfNames[PK_N] = {
     "k_match_round", "k_match_free", "k_match_settle", "k_hub", "k_twohop", "k_iso",
     "k_contract_count",
-    "k_contract_map", "k_contract_rows", "k_contract_long", "k_contract_huge",
+    "k_contract_map", "k_contract_short", "k_contract_rows", "k_contract_long", "k_contract_huge",
     "k_contract_compact", "k_init_tot",
     "k_init_trials", "k_refine_gain", "k_refine_scan", "k_refine_delta", "k_refine_settle",
     "k_refine_apply", "k_project", "k_final_stats"};
@@ -607,7 +607,6 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   const int ntc1 = ntc > 0 ? ntc : 1;
   {
     // algorithmic bytes are set after the level (they depend on the long rows)
-    ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
     // rows of <= 32 candidates; the others are listed per segment in
     // sc.tmpk (free here; at least n slots), with their counts in
     // sc.partials, then sorted by the row kernel
@@ -615,8 +614,12 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
                   "partials hold the segment counts");
     const int nseg = grid_for((int64_t)nc_max * 32, kBlock, kContractSegMax);
     int32_t* dcnt = (int32_t*)sc.partials;
-    k_contract_short<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
-                                             cw, sc.cnt, sc.tmpk, dcnt);
+    {
+      ProfScope ps(PK_CONTRACT_SHORT, 0, 0.0, s);
+      k_contract_short<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
+                                               cw, sc.cnt, sc.tmpk, dcnt);
+    }
+    ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
     k_contract_rows<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,
                                             sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1, sc.prop,
                                             sc.tmpk, dcnt);

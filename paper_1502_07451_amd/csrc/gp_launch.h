@@ -38,7 +38,7 @@ int team_width_for(int32_t n, int64_t nnz);
 // ---- per-launch profiling (HIP events), enabled by the driver for one call
 enum ProfKind {
   PK_MATCH_ROUND, PK_MATCH_FREE, PK_MATCH_SETTLE, PK_HUB, PK_TWOHOP, PK_ISO, PK_CONTRACT_COUNT,
-  PK_CONTRACT_MAP, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_HUGE, PK_CONTRACT_COMPACT,
+  PK_CONTRACT_MAP, PK_CONTRACT_SHORT, PK_CONTRACT_ROWS, PK_CONTRACT_LONG, PK_CONTRACT_HUGE, PK_CONTRACT_COMPACT,
   PK_INIT_TOT,
   PK_INIT_TRIALS, PK_REFINE_GAIN, PK_REFINE_SCAN, PK_REFINE_DELTA, PK_REFINE_SETTLE,
   PK_REFINE_APPLY, PK_PROJECT, PK_FINAL_STATS, PK_N

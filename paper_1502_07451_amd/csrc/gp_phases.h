@@ -33,6 +33,9 @@ __device__ __forceinline__ void b_level_reset(Ctrl* ctrl, int promote, int bid_,
     ctrl->nhuge = 0;
     ctrl->huge_in = 0;
     ctrl->huge_out = 0;
+    ctrl->short_in = 0;
+    ctrl->short_out = 0;
+    ctrl->deferred = 0;
     ctrl->maxb_next = 0;
   }
 }
@@ -773,12 +776,14 @@ __device__ __forceinline__ void b_contract_rows(
 // the large sparse levels.
 __device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cmap,
                                                  const int32_t* cmem0, const int32_t* cmem1,
-                                                 const int64_t* toff, const Ctrl* ctrl,
+                                                 const int64_t* toff, Ctrl* ctrl,
                                                  int32_t* okey, int64_t* oval, int32_t* cnt,
                                                  int32_t* defer, int32_t* dcnt, int seg,
                                                  int nseg) {
   constexpr int T = 32;
   __shared__ int32_t s_nd;
+  __shared__ int64_t sml[kBlock / 64];
+  int64_t rin = 0, rout = 0;  // candidates read and entries written (lane 0 of each team)
   if (threadIdx.x == 0) s_nd = 0;
   __syncthreads();
   const int lane = threadIdx.x & (T - 1);
@@ -807,9 +812,19 @@ __device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cm
     ld.d0 = x0 - e0;
     ld.e1 = e1;
     team_row<T>(ld, L, okey + o, oval + o, &cnt[c]);
+    if (lane == 0) {
+      rin += L;
+      rout += cnt[c];
+    }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) dcnt[seg] = s_nd;
+  rin = block_sum<kBlock, int64_t>(rin, sml);
+  rout = block_sum<kBlock, int64_t>(rout, sml);
+  if (threadIdx.x == 0) {
+    dcnt[seg] = s_nd;
+    if (s_nd) atomicAdd((unsigned long long*)&ctrl->deferred, (unsigned long long)s_nd);
+    if (rin) atomicAdd((unsigned long long*)&ctrl->short_in, (unsigned long long)rin);
+    if (rout) atomicAdd((unsigned long long*)&ctrl->short_out, (unsigned long long)rout);
+  }
 }
 
 // exclusive scan of the coarse-tile entry counts; their total is 2m of the
