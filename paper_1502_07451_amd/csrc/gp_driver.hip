@@ -169,7 +169,7 @@ struct gp_graph {
            toff.ensure(n1) && cnt.ensure(n1) && tile_cnt.ensure(n1 / kTileC + 2) &&
            tmpk.ensure(nnz > n1 ? nnz : n1) && tmpv.ensure(nnz) && longlist.ensure(n1) &&
            list.ensure(n1) &&
-           partials.ensure(5 * 4096) && r_ext.ensure(n1) && r_inn.ensure(n1) &&
+           partials.ensure(kPartials) && r_ext.ensure(n1) && r_inn.ensure(n1) &&
            r_mark.ensure(n1);
   }
   bool ensure_init(int32_t nl, int K) {
@@ -600,7 +600,7 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     // the level's part array is free until the uncoarsening (the free
     // flags), the contraction's member lists and the reduction partials
     // until the contraction (the free lists and their lengths)
-    static_assert(5 * 4096 * sizeof(int64_t) >= 2 * kMatchSegMax * sizeof(int32_t),
+    static_assert(kPartials * sizeof(int64_t) >= 2 * kMatchSegMax * sizeof(int32_t),
                   "partials hold both list-length arrays");
     LCHK(launch_match_rounds(fv, f->match.p, (uint8_t*)f->part.p, sc.cmem0, sc.cmem1,
                              (int32_t*)sc.partials, sc.prop, sc.longlist, g->ctrl, R, hs, tw,

@@ -15,6 +15,7 @@ constexpr int kBlock = 256;       // threads per block of the level kernels
 constexpr int kTileV = 1024;      // vertices per tile of the ordered-scan kernels
 constexpr int kMatchSegMax = 4096;  // blocks (list segments) of a matching round
 constexpr int kContractSegMax = 16384;  // blocks (row segments) of the short-row kernel
+constexpr int kPartials = 5 * 8192;  // int64 scratch of the reductions and the segment lists
 constexpr int kTileC = 64;        // coarse rows per tile of the row-sort kernel
 constexpr int kWaveCap = 512;     // longest candidate row sorted in LDS by one wave
 constexpr int kRowBlockCap = 2048;  // longest candidate row sorted in LDS by one block (contraction)

@@ -126,12 +126,18 @@ __global__ __launch_bounds__(kBlock) void k_contract_map(LevelView lv, const int
 __global__ __launch_bounds__(kBlock) void k_contract_short(LevelView lv, const int32_t* cmap,
                                                            const int32_t* cmem0,
                                                            const int32_t* cmem1,
-                                                           const int64_t* toff, Ctrl* ctrl,
-                                                           int32_t* okey, int64_t* oval,
-                                                           int32_t* cnt, int32_t* defer,
-                                                           int32_t* dcnt) {
-  b_contract_short(lv, cmap, cmem0, cmem1, toff, ctrl, okey, oval, cnt, defer, dcnt,
+                                                           const int64_t* toff,
+                                                           const Ctrl* ctrl, int32_t* okey,
+                                                           int64_t* oval, int32_t* cnt,
+                                                           int32_t* defer, int32_t* dcnt,
+                                                           int64_t* sio) {
+  b_contract_short(lv, cmap, cmem0, cmem1, toff, ctrl, okey, oval, cnt, defer, dcnt, sio,
                    (int)blockIdx.x, (int)gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_contract_sums(Ctrl* ctrl, const int32_t* dcnt,
+                                                          const int64_t* sio, int nseg) {
+  b_contract_sums(ctrl, dcnt, sio, nseg);
 }
 
 // the rows the short-row kernel listed, block k taking segment k's, 16 at a
@@ -610,15 +616,18 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     // rows of <= 32 candidates; the others are listed per segment in
     // sc.tmpk (free here; at least n slots), with their counts in
     // sc.partials, then sorted by the row kernel
-    static_assert(5 * 4096 * sizeof(int64_t) >= kContractSegMax * sizeof(int32_t),
-                  "partials hold the segment counts");
+    static_assert(kPartials >= kContractSegMax / 2 + 2 * kContractSegMax,
+                  "partials hold the segment counts and totals");
     const int nseg = grid_for((int64_t)nc_max * 32, kBlock, kContractSegMax);
     int32_t* dcnt = (int32_t*)sc.partials;
+    int64_t* sio = sc.partials + kContractSegMax / 2;
     {
       ProfScope ps(PK_CONTRACT_SHORT, 0, 0.0, s);
       k_contract_short<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
-                                               cw, sc.cnt, sc.tmpk, dcnt);
+                                               cw, sc.cnt, sc.tmpk, dcnt, sio);
     }
+    // the profiler's byte count of the two row kernels needs the totals
+    if (g_prof) k_contract_sums<<<1, kBlock, 0, s>>>(ctrl, dcnt, sio, nseg);
     ProfScope ps(PK_CONTRACT_ROWS, 0, 0.0, s);
     k_contract_rows<<<nseg, kBlock, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,
                                             sc.cnt, sc.tile_cnt, sc.longlist, ctrl, ntc1, sc.prop,
@@ -632,8 +641,10 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     // every coarse row may be long: up to one wave per row, at most the ten
     // waves per compute unit that the LDS holds
     const int gw = nc_max < 2560 ? (nc_max > 0 ? nc_max : 1) : 2560;
+    // (no tile counts: only the coarsest level's compaction needs them, and
+    // it recounts them from the row lengths)
     k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,
-                                      sc.cnt, sc.tile_cnt, sc.longlist);
+                                      sc.cnt, nullptr, sc.longlist);
   }
   KCHECK();
   // the dense window plus a staged copy of one row (96 KB)
@@ -649,7 +660,7 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
     // up to one block per row; one block per compute unit fits the LDS
     const int glong = nc_max < 512 ? (nc_max > 0 ? nc_max : 1) : 512;
     k_contract_huge<<<glong, kBlock, dyn, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj,
-                                               cw, sc.cnt, sc.tile_cnt, sc.prop, ntc1);
+                                               cw, sc.cnt, nullptr, sc.prop, ntc1);
   }
   KCHECK();
   k_contract_ends<<<grid_for(nc_max, kBlock), kBlock, 0, s>>>(ctrl, sc.toff, sc.cnt, cxadj,

@@ -619,9 +619,10 @@ __device__ __forceinline__ CoarseRowLoader coarse_loader(const LevelView& lv, co
   return ld;
 }
 
+// returns the row's entry count (also stored to *cnt_out)
 template <int T>
-__device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32_t* okey,
-                                         int64_t* oval, int32_t* cnt_out) {
+__device__ __forceinline__ int team_row(const CoarseRowLoader& ld, int L, int32_t* okey,
+                                        int64_t* oval, int32_t* cnt_out) {
   const int lane = threadIdx.x & (T - 1);
   int32_t k = INT_MAX;
   int64_t v = 0;
@@ -630,6 +631,7 @@ __device__ __forceinline__ void team_row(const CoarseRowLoader& ld, int L, int32
   bool dummy = false;
   int cnt = team_emit<T, true>(k, v, okey, oval, &dummy);
   if (lane == 0) *cnt_out = cnt;
+  return cnt;
 }
 
 __device__ __forceinline__ int wave_row_packed(const LevelView& lv, const int32_t* cmap,
@@ -670,14 +672,16 @@ __device__ __forceinline__ void b_contract_rows(
   if (rowlist) rowlist += bid_ * S;
   const int wave = threadIdx.x / 64;
   const int32_t ngroups = (nrow + R - 1) / R;
+  int64_t li_acc = 0, hi_acc = 0;  // candidates of the rows listed (thread 0)
   for (int32_t grp = rowlist ? 0 : bid_; grp < ngroups; grp += rowlist ? 1 : nblk_) {
     const int32_t c0 = grp * R;
     const int rows = c0 + R < nrow ? R : nrow - c0;
     if (threadIdx.x < 64) {
       // wave 0 reads the rows' members and sorts the rows into classes
       int L = 0;
+      int32_t c = 0;
       if ((int)threadIdx.x < rows) {
-        const int32_t c = rowlist ? rowlist[c0 + threadIdx.x] : c0 + (int32_t)threadIdx.x;
+        c = rowlist ? rowlist[c0 + threadIdx.x] : c0 + (int32_t)threadIdx.x;
         s_c[threadIdx.x] = c;
         const int32_t m0 = cmem0[c], m1 = cmem1[c];
         const int32_t e0 = lv.xadj[m0], d0 = lv.xend[m0] - e0;
@@ -688,21 +692,31 @@ __device__ __forceinline__ void b_contract_rows(
         s_d0[threadIdx.x] = d0;
         s_e1[threadIdx.x] = e1;
         s_len[threadIdx.x] = L;
-        if (L > kWaveCap) {
-          // one wave per row when the packed keys fit, else one block per row
-          if (!hugelist || (L <= kLongCap && nc < kPackMaxNc)) {
-            const int slot = atomicAdd(&wctrl->nlong, 1);
-            longlist[slot] = c;
-            atomicAdd((unsigned long long*)&wctrl->long_in, (unsigned long long)L);
-          } else {
-            const int slot = atomicAdd(&wctrl->nhuge, 1);
-            hugelist[slot] = c;
-            atomicAdd((unsigned long long*)&wctrl->huge_in, (unsigned long long)L);
-          }
-          cnt[c] = 0;
-        }
       }
       const bool in_rows = (int)threadIdx.x < rows;
+      // rows beyond kWaveCap: one wave per row when the packed keys fit,
+      // else one block per row; listed with one counter update per group
+      const bool is_long =
+          in_rows && L > kWaveCap && (!hugelist || (L <= kLongCap && nc < kPackMaxNc));
+      const bool is_huge = in_rows && L > kWaveCap && !is_long;
+      const uint64_t ml = __ballot(is_long), mh = __ballot(is_huge);
+      if (ml | mh) {
+        int bl = 0, bh = 0;
+        if (threadIdx.x == 0) {
+          if (ml) bl = atomicAdd(&wctrl->nlong, (int)__popcll(ml));
+          if (mh) bh = atomicAdd(&wctrl->nhuge, (int)__popcll(mh));
+        }
+        bl = __shfl(bl, 0, 64);
+        bh = __shfl(bh, 0, 64);
+        const uint64_t lt = lanemask_lt();
+        if (is_long) longlist[bl + __popcll(ml & lt)] = c;
+        if (is_huge) hugelist[bh + __popcll(mh & lt)] = c;
+        if (is_long || is_huge) cnt[c] = 0;
+        const int64_t sl = team_sum<64, int64_t>(is_long ? (int64_t)L : 0);
+        const int64_t sh = team_sum<64, int64_t>(is_huge ? (int64_t)L : 0);
+        li_acc += sl;
+        hi_acc += sh;
+      }
       const bool cls[3] = {in_rows && L > 16 && L <= 32, in_rows && L > 32 && L <= 64,
                            in_rows && L > 64 && L <= kWaveCap};
 #pragma unroll
@@ -765,6 +779,10 @@ __device__ __forceinline__ void b_contract_rows(
         atomicAdd((unsigned long long*)&tile_cnt[c0 / kTileC], (unsigned long long)sum);
     }
   }
+  if (threadIdx.x == 0) {
+    if (li_acc) atomicAdd((unsigned long long*)&wctrl->long_in, (unsigned long long)li_acc);
+    if (hi_acc) atomicAdd((unsigned long long*)&wctrl->huge_in, (unsigned long long)hi_acc);
+  }
 }
 
 // Rows of at most 32 candidates, one 32-lane team each: the team reads its
@@ -776,10 +794,10 @@ __device__ __forceinline__ void b_contract_rows(
 // the large sparse levels.
 __device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cmap,
                                                  const int32_t* cmem0, const int32_t* cmem1,
-                                                 const int64_t* toff, Ctrl* ctrl,
+                                                 const int64_t* toff, const Ctrl* ctrl,
                                                  int32_t* okey, int64_t* oval, int32_t* cnt,
-                                                 int32_t* defer, int32_t* dcnt, int seg,
-                                                 int nseg) {
+                                                 int32_t* defer, int32_t* dcnt, int64_t* sio,
+                                                 int seg, int nseg) {
   constexpr int T = 32;
   __shared__ int32_t s_nd;
   __shared__ int64_t sml[kBlock / 64];
@@ -811,19 +829,40 @@ __device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cm
     ld.e0 = e0;
     ld.d0 = x0 - e0;
     ld.e1 = e1;
-    team_row<T>(ld, L, okey + o, oval + o, &cnt[c]);
+    const int k = team_row<T>(ld, L, okey + o, oval + o, &cnt[c]);
     if (lane == 0) {
       rin += L;
-      rout += cnt[c];
+      rout += k;
     }
   }
+  // per-block totals (no shared counter: device-wide atomics from every
+  // block would serialize); summed only for the profiler (b_contract_sums)
   rin = block_sum<kBlock, int64_t>(rin, sml);
   rout = block_sum<kBlock, int64_t>(rout, sml);
   if (threadIdx.x == 0) {
     dcnt[seg] = s_nd;
-    if (s_nd) atomicAdd((unsigned long long*)&ctrl->deferred, (unsigned long long)s_nd);
-    if (rin) atomicAdd((unsigned long long*)&ctrl->short_in, (unsigned long long)rin);
-    if (rout) atomicAdd((unsigned long long*)&ctrl->short_out, (unsigned long long)rout);
+    sio[2 * seg] = rin;
+    sio[2 * seg + 1] = rout;
+  }
+}
+
+// the short-row kernel's per-block totals into the control block (one block)
+__device__ __forceinline__ void b_contract_sums(Ctrl* ctrl, const int32_t* dcnt,
+                                                const int64_t* sio, int nseg) {
+  __shared__ int64_t sml[kBlock / 64];
+  int64_t d = 0, a = 0, b = 0;
+  for (int i = threadIdx.x; i < nseg; i += kBlock) {
+    d += dcnt[i];
+    a += sio[2 * i];
+    b += sio[2 * i + 1];
+  }
+  d = block_sum<kBlock, int64_t>(d, sml);
+  a = block_sum<kBlock, int64_t>(a, sml);
+  b = block_sum<kBlock, int64_t>(b, sml);
+  if (threadIdx.x == 0) {
+    ctrl->deferred = d;
+    ctrl->short_in = a;
+    ctrl->short_out = b;
   }
 }
 
@@ -864,6 +903,7 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
   __shared__ int64_t sml[kBlock / 64];
   // huge: the rows that the row kernel listed for one block each
   const int32_t nlong = huge ? ctrl->nhuge : ctrl->nlong;
+  int64_t out_acc = 0;  // entries written (thread 0), one counter update per block
   for (int32_t i = bid_; i < nlong; i += nblk_) {
     const int32_t c = longlist[i];
     int L;
@@ -907,11 +947,13 @@ __device__ __forceinline__ void b_contract_long(LevelView lv, const int32_t* cma
     }
     if (threadIdx.x == 0) {
       cnt[c] = k;
-      atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
-      atomicAdd((unsigned long long*)(huge ? &ctrl->huge_out : &ctrl->long_out),
-                (unsigned long long)k);
+      if (tile_cnt) atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)k);
+      out_acc += k;
     }
   }
+  if (threadIdx.x == 0 && out_acc)
+    atomicAdd((unsigned long long*)(huge ? &ctrl->huge_out : &ctrl->long_out),
+              (unsigned long long)out_acc);
   if (!inline_tail) return;
   __syncthreads();
   b_tile_scan(ctrl, tile_cnt, ntiles_c);
@@ -1043,6 +1085,7 @@ __device__ __forceinline__ void b_contract_longw(LevelView lv, const int32_t* cm
                                                  const int32_t* longlist, int32_t* sk, int wid,
                                                  int nw) {
   const int32_t nlong = ctrl->nlong;
+  int64_t out_acc = 0;  // entries written (lane 0), one counter update per wave
   for (int32_t i = wid; i < nlong; i += nw) {
     const int32_t c = longlist[i];
     int L;
@@ -1050,10 +1093,13 @@ __device__ __forceinline__ void b_contract_longw(LevelView lv, const int32_t* cm
     const int total = wave_row_packed(lv, cmap, ld, c, L, sk, tmpk + toff[c], tmpv + toff[c]);
     if (lane_id() == 0) {
       cnt[c] = total;
-      atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)total);
-      atomicAdd((unsigned long long*)&ctrl->long_out, (unsigned long long)total);
+      if (tile_cnt)
+        atomicAdd((unsigned long long*)&tile_cnt[c / kTileC], (unsigned long long)total);
+      out_acc += total;
     }
   }
+  if (lane_id() == 0 && out_acc)
+    atomicAdd((unsigned long long*)&ctrl->long_out, (unsigned long long)out_acc);
 }
 
 __device__ __forceinline__ void b_contract_compact(const Ctrl* ctrl,
