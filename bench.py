@@ -112,6 +112,38 @@ def roofline_of(agg, workload):
     return roof
 
 
+def batch_timeline(bt, bb, chosen):
+    """What sets the batched kernel's time, from the per-graph start and end
+    ticks of the last call: the span, how long every workgroup stayed busy,
+    the tail after the first one ran dry, and the graphs that finished last."""
+    import numpy as np
+    G = len(bb.voff) - 1
+    t, hz = bt.timeline(G)
+    t = (t - t[:, 0].min()).astype(np.float64) * 1e3 / hz  # ms from the first start
+    span = float(t[:, 1].max())
+    # workgroups busy at once: +1 at each start, -1 at each end
+    ev = sorted([(a, 1) for a in t[:, 0]] + [(b, -1) for b in t[:, 1]])
+    busy, peak = 0, 0
+    for x, d in ev:
+        busy += d
+        peak = max(peak, busy)
+    queue_empty = float(t[:, 0].max())  # the last graph is taken
+    dur = t[:, 1] - t[:, 0]
+    n = np.diff(bb.voff)
+    last = np.argsort(t[:, 1])[-5:][::-1]
+    big = n >= np.percentile(n, 90)
+    return {"span_ms": round(span, 3), "workgroups_busy": int(peak),
+            "queue_empty_ms": round(queue_empty, 3),
+            "tail_ms": round(span - queue_empty, 3),
+            "graph_ms_p50": round(float(np.median(dur)), 3),
+            "graph_ms_max": round(float(dur.max()), 3),
+            "largest_decile_graph_ms_mean": round(float(dur[big].mean()), 3),
+            "last_finished": [{"graph": int(g), "vertices": int(n[g]),
+                               "ms": round(float(dur[g]), 3),
+                               "end_ms": round(float(t[g, 1]), 3)} for g in last],
+            "sum_graph_ms_over_workgroups": round(float(dur.sum()) / max(peak, 1), 3)}
+
+
 def cpu_model_name() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -383,6 +415,7 @@ def main():
                             "autotuned": {"workgroups": chosen[0], "chunk": chosen[1],
                                           "order_mode": chosen[2],
                                           "tuning_ms_per_call": round(tune_ms, 3)}}
+        out["batch4096"]["timeline"] = batch_timeline(bt, bb, chosen)
         gotb = pb.cpu().numpy()
         bt.close()
         del dev_b, pb

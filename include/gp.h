@@ -270,6 +270,13 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
                              const int64_t* vwgt, const gp_options* o, int8_t* part,
                              gp_result* res);
 void gp_batch_destroy(gp_batch* b);
+/* Timeline of the last successful gp_partition_batch call on b, to see what
+ * sets its time (a long graph at the end, or every workgroup busy to the
+ * end): ticks (host int64[2G]) receives, for graph g, the device wall clock
+ * when a workgroup took it (2g) and when it finished it (2g + 1); *hz (may
+ * be NULL) the clock's rate.  A graph redone after running out of arena
+ * shows its last run.  G above the last call's count: GP_EINVAL. */
+gp_status gp_batch_timeline(gp_batch* b, int32_t G, int64_t* ticks, int64_t* hz);
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): gp_partition_batch with
  * no allocation of any kind.  Its scratch is one fixed 64 MiB device array

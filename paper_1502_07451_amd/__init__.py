@@ -127,6 +127,8 @@ def _load():
     lib.gp_profile_read.restype = i32
     lib.gp_batch_create.argtypes = [ctypes.POINTER(vp), vp]
     lib.gp_batch_create.restype = ctypes.c_int
+    lib.gp_batch_timeline.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
+    lib.gp_batch_timeline.restype = ctypes.c_int
     lib.gp_batch_config.argtypes = [vp, i32, i32, i32]
     lib.gp_batch_config.restype = ctypes.c_int
     lib.gp_partition_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options),
@@ -422,6 +424,15 @@ class Batch:
                                       int(adjncy.numel()))
         if st != OK:
             raise GPError(st, "gp_batch_export")
+
+    def timeline(self, G: int):
+        """(ticks int64[G, 2]: start / end of each graph of the last call, clock rate in Hz)."""
+        t = np.zeros((max(int(G), 1), 2), np.int64)
+        hz = ctypes.c_int64()
+        st = _lib.gp_batch_timeline(self._h, int(G), t.ctypes.data, ctypes.byref(hz))
+        if st != OK:
+            raise GPError(st, "gp_batch_timeline")
+        return t[:G], int(hz.value)
 
     def config(self, workgroups: int = 0, chunk: int = 1, order_mode: int = 0):
         st = _lib.gp_batch_config(self._h, workgroups, chunk, order_mode)

@@ -27,6 +27,20 @@ namespace gpk {
 
 constexpr int kBatchLevels = kMaxLevels + 1;
 
+// dynamic LDS of the persistent kernel: the dense window of the long-row
+// merge (kWin x 12 bytes) and, in the same bytes, an LDS-resident trial of up
+// to kBatchTrialMax vertices.  48 KB plus the kernel's static LDS stay under
+// half of a compute unit's 160 KB, so two workgroups share each unit; larger
+// coarsest graphs take the global-memory trial form.
+constexpr size_t kBatchLds = 48 * 1024;
+constexpr int kBatchTrialMax =
+    (int)((kBatchLds - trial_lds_bytes(0, kBlock)) / 23) < kTrialLdsMax
+        ? (int)((kBatchLds - trial_lds_bytes(0, kBlock)) / 23)
+        : kTrialLdsMax;
+static_assert(trial_lds_bytes(kBatchTrialMax, kBlock) <= kBatchLds, "trial state exceeds the LDS");
+static_assert((size_t)kWin * 12 <= kBatchLds && (size_t)kRowBlockCap * 12 <= kBatchLds,
+              "contraction buffers exceed the LDS");
+
 struct LevelRec {
   int32_t n;
   int32_t nnz;
@@ -82,6 +96,7 @@ struct BatchArgs {
   int32_t nnzmax;
   int32_t chunk;
   ExportArgs ex;  // ex.rec == nullptr: no export
+  int64_t* tline; // per graph: wall-clock ticks when its workgroup took it and finished it
 };
 
 // per-workgroup scratch carved from wgs + blockIdx.x * wgs_stride
@@ -401,7 +416,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     const int gs = a.r0 <= a.r1 ? 0 : 1;
     b_init_tot(cv, ws.tot, 0, 1);
     __syncthreads();
-    if (cl.n <= kTrialLdsMax) {
+    if (cl.n <= kBatchTrialMax) {
       for (int t = 0; t < K; t++)
         b_trial_lds<kBlock>(cv, ws.tot, K, t, gs, a.P, ctrl, ws.tctl, ws.tpart, ws.tres, lds, sel,
                             srf);
@@ -420,7 +435,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
                                sel);
       b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, tp, ws.tres, cl.part);
     }
-    if (cl.n <= kTrialLdsMax) b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, ws.tpart, ws.tres, cl.part);
+    if (cl.n <= kBatchTrialMax) b_trial_pick<kBlock>(K, cl.n, ctrl, ws.tctl, ws.tpart, ws.tres, cl.part);
     __syncthreads();
     if (a.ex.rec) {
       __shared__ long long s_vs, s_es;
@@ -506,15 +521,10 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   __syncthreads();
 }
 
-// dynamic LDS of the persistent kernel: the largest phase is an LDS-resident
-// initial-bisection trial (70,932 bytes at 3,072 vertices); two workgroups of
-// 72 KB plus their static LDS fit a compute unit's 160 KB
-constexpr size_t kBatchLds = 72 * 1024;
-static_assert(trial_lds_bytes(kTrialLdsMax, kBlock) <= kBatchLds, "trial state exceeds the LDS");
-static_assert((size_t)kWin * 12 <= kBatchLds && (size_t)kRowBlockCap * 12 <= kBatchLds,
-              "contraction buffers exceed the LDS");
 
-__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
+
+// two waves per SIMD: two workgroups share each compute unit (their LDS fits)
+__global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ SelShared sel;
   __shared__ RefCtl srf;
@@ -527,7 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
     __syncthreads();
     if (first >= a.G) break;
     const int last = first + a.chunk < a.G ? first + a.chunk : a.G;
-    for (int i = first; i < last; i++) batch_graph(a, a.order ? a.order[i] : i, ws, lds, &sel, &srf);
+    for (int i = first; i < last; i++) {
+      const int g = a.order ? a.order[i] : i;
+      int64_t t0 = 0;
+      if (a.tline && threadIdx.x == 0) t0 = (int64_t)wall_clock64();
+      batch_graph(a, g, ws, lds, &sel, &srf);  // ends with a barrier
+      if (a.tline && threadIdx.x == 0) {
+        a.tline[2 * g] = t0;
+        a.tline[2 * g + 1] = (int64_t)wall_clock64();
+      }
+    }
   }
 }
 
@@ -583,6 +602,8 @@ struct gp_batch {
   int order_mode = 0;   // 0: largest first, 1: input order
   HBuf<unsigned char> wgs, arena;
   HBuf<int32_t> order;
+  HBuf<int64_t> tline;  // per-graph start / end ticks of the last call
+  int32_t tline_g = 0;  // graphs they cover
   HBuf<gp_result> res;
   HBuf<uint32_t> head;
   HBuf<unsigned long long> arena_off;
@@ -603,7 +624,8 @@ struct gp_batch {
   ~gp_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    wgs.release(); arena.release(); order.release(); res.release(); head.release();
+    wgs.release(); arena.release(); order.release(); tline.release(); res.release();
+    head.release();
     arena_off.release();
     ex_heads.release();
     if (hres) (void)hipHostFree(hres);
@@ -776,7 +798,8 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   const uint64_t arena_bytes =
       (uint64_t)(b->arena_factor * (double)(ntot * 57 + mtot * 12)) + (uint64_t)G * 8192 + (1 << 20);
   if (!b->wgs.ensure((size_t)stride * nwg) || !b->arena.ensure(arena_bytes) ||
-      !b->order.ensure(G) || !b->res.ensure(G) || !b->head.ensure(1) || !b->arena_off.ensure(1))
+      !b->order.ensure(G) || !b->tline.ensure(2 * (size_t)G) || !b->res.ensure(G) ||
+      !b->head.ensure(1) || !b->arena_off.ensure(1))
     return GP_ENOMEM;
   if (b->hres_cap < (size_t)G) {
     if (b->hres) (void)hipHostFree(b->hres);
@@ -820,6 +843,8 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   a.nnzmax = (int32_t)nnzmax;
   a.chunk = b->chunk;
   a.ex = b->ex;
+  a.tline = b->tline.p;
+  b->tline_g = 0;
   if ((st = batch_launch(b, a, nwg)) != GP_OK) return st;
   if (hipMemcpyAsync(b->hres, b->res.p, sizeof(gp_result) * G, hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
@@ -849,6 +874,27 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
       return GP_EDEVICE;
   }
   memcpy(res, b->hres, sizeof(gp_result) * G);
+  b->tline_g = G;
+  return GP_OK;
+}
+
+gp_status gp_batch_timeline(gp_batch* b, int32_t G, int64_t* ticks, int64_t* hz) {
+  if (!b || G < 0 || G > b->tline_g || (G > 0 && !ticks)) return GP_EINVAL;
+  if (hz) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return GP_EDEVICE;
+    }
+    *hz = (int64_t)khz * 1000;
+  }
+  if (G > 0 && (hipMemcpyAsync(ticks, b->tline.p, sizeof(int64_t) * 2 * (size_t)G,
+                               hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+                hipStreamSynchronize(b->stream) != hipSuccess)) {
+    (void)hipGetLastError();
+    return GP_EDEVICE;
+  }
   return GP_OK;
 }
 

@@ -271,13 +271,19 @@ __device__ __forceinline__ u128 cand_key(const Cand& c, int64_t gmin, int idbits
   return ((u128)g << idbits) | (u128)idpart;
 }
 
+constexpr int kSelSmall = 256;
+
+// block-shared state of the threshold search; the small-list buffers live
+// here (one copy per block, whatever the candidate source)
 struct SelShared {
   int64_t hist[256];
   u128 prefix;
   int64_t above;
   int done;
-  int pad;
+  int scnt;
   u128 result;
+  alignas(16) uint64_t skey[2 * kSelSmall];  // key words interleaved
+  int64_t sw[kSelSmall];
 };
 
 // Candidate sources for the threshold search: a compacted list, or every
@@ -345,16 +351,14 @@ struct LdsItems {
 //            -> 0; else the key at which the running sum first reaches bound;
 //   else:    bound < 0 -> that all-ones key + 1; total <= bound -> 0; else the
 //            key at which the running sum first exceeds bound, + 1.
-constexpr int kSelSmall = 256;
-
 template <int BS, class Items>
 __device__ u128 select_small(const Items& items, int64_t gmin, int idbits, int tbits, int want_ge,
                              int64_t bound, SelShared* sh) {
   // key words interleaved (one 16-byte read per key), padded to a multiple
   // of 8 with key 0 and weight 0, which change no running sum
-  __shared__ __align__(16) uint64_t s_key[2 * kSelSmall];
-  __shared__ int64_t s_w[kSelSmall];
-  __shared__ int s_cnt;
+  uint64_t* s_key = sh->skey;
+  int64_t* s_w = sh->sw;
+  int& s_cnt = sh->scnt;
   const int ndig = (tbits + 7) / 8;
   const u128 ones = (((u128)1) << (8 * ndig)) - 1;
   if (want_ge ? bound <= 0 : bound < 0) return want_ge ? ones : ones + 1;

@@ -183,3 +183,23 @@ def test_batch_autotune_keeps_results(gp):
     assert np.array_equal(part2.cpu().numpy(), got)
     assert [r.as_dict() for r in res2] == [r.as_dict() for r in res]
     bt.close()
+
+
+def test_batch_timeline(gp):
+    """gp_batch_timeline: every graph of the last call has a start and an end
+    on the device clock, in order; asking for more graphs than it ran is
+    refused."""
+    graphs = [dagen.layered(int(n), 6, rate=3, seed=i)
+              for i, n in enumerate(np.linspace(200, 5000, 24).astype(int))]
+    bb = dagen.concat(graphs)
+    say("case batch timeline 24")
+    b = gp.Batch()
+    _, res = b.partition(*gp.batch_to_device(bb))
+    assert all(r.status == 0 for r in res)
+    t, hz = b.timeline(len(graphs))
+    assert hz > 0 and t.shape == (len(graphs), 2)
+    assert (t[:, 0] > 0).all() and (t[:, 1] >= t[:, 0]).all()
+    with pytest.raises(gp.GPError) as e:
+        b.timeline(len(graphs) + 1)
+    assert e.value.status == gp.EINVAL
+    b.close()
