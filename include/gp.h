@@ -262,8 +262,10 @@ typedef struct gp_batch gp_batch;
 /* A batch context owning the device scratch (reused by later calls). */
 gp_status gp_batch_create(gp_batch** b, void* stream);
 /* workgroups: persistent workgroups (0 = two per compute unit); chunk:
- * graphs taken per queue pop; order_mode: 0 largest first, 1 input order.
- * None of them changes any result. */
+ * graphs taken per queue pop; order_mode: 0 largest first, 1 input order,
+ * 2 the graphs that took longest in the previous call of the same batch
+ * size on b first (largest first without one).  None of them changes any
+ * result. */
 gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode);
 gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
                              const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
@@ -298,8 +300,9 @@ gp_status gp_partition_batch_noalloc(int32_t G, const int64_t* voff, const int64
                                      int64_t ntot, int64_t nnztot, int8_t* part,
                                      gp_result* res, void* stream);
 /* Autotuner of the batched path: runs gp_partition_batch with each of 18
- * configurations (1, 2 or 3 persistent workgroups per compute unit x 1, 2
- * or 4 graphs per queue pop x largest-first or input order), checks that
+ * configurations (1 or 2 persistent workgroups per compute unit x 1, 2 or 4
+ * graphs per queue pop x largest-first, input or previous-longest-first
+ * order), checks that
  * every configuration returns byte-identical part and res, times `reps`
  * calls of each (host wall clock, whole calls), and keeps the fastest in b
  * for later calls.  chosen (host int32[3], may be NULL) receives workgroups,

@@ -599,7 +599,7 @@ struct gp_batch {
   hipStream_t stream = nullptr;
   int nwg = 0;          // persistent workgroups (0: 2 per compute unit)
   int chunk = 1;        // graphs per queue pop
-  int order_mode = 0;   // 0: largest first, 1: input order
+  int order_mode = 0;   // 0: largest first, 1: input order, 2: previous call's longest first
   HBuf<unsigned char> wgs, arena;
   HBuf<int32_t> order;
   HBuf<int64_t> tline;  // per-graph start / end ticks of the last call
@@ -738,7 +738,7 @@ gp_status gp_batch_export(gp_batch* b, int64_t* rec, int32_t* xadj, int64_t* vwg
 }
 
 gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode) {
-  if (!b || workgroups < 0 || chunk < 1 || chunk > 64 || order_mode < 0 || order_mode > 1)
+  if (!b || workgroups < 0 || chunk < 1 || chunk > 64 || order_mode < 0 || order_mode > 2)
     return GP_EINVAL;
   b->nwg = workgroups;
   b->chunk = chunk;
@@ -785,13 +785,26 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   }
   const int64_t ntot = hv[G], mtot = he[G];
   if ((ntot > 0 && !adjncy && mtot > 0) || (mtot > 0 && !adjwgt)) return GP_EINVAL;
-  // processing order: largest graphs first (or input order)
+  // processing order: largest graphs first, input order, or the longest
+  // graphs of the previous call on this context first (longest processing
+  // time first: the timeline tells which graphs are slow, e.g. those whose
+  // coarsening stalls; without a previous call of G graphs, largest first)
   std::vector<int32_t> ord(G);
   std::iota(ord.begin(), ord.end(), 0);
-  if (b->order_mode == 0)
+  if (b->order_mode == 2 && b->tline_g == G && G > 0) {
+    std::vector<int64_t> t(2 * (size_t)G);
+    if (hipMemcpyAsync(t.data(), b->tline.p, sizeof(int64_t) * 2 * (size_t)G,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GP_EDEVICE;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return t[2 * x + 1] - t[2 * x] > t[2 * y + 1] - t[2 * y];
+    });
+  } else if (b->order_mode != 1) {
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
       return (he[x + 1] - he[x]) + (hv[x + 1] - hv[x]) > (he[y + 1] - he[y]) + (hv[y + 1] - hv[y]);
     });
+  }
   const int nwg = b->nwg > 0 ? b->nwg : 2 * (b->cus > 0 ? b->cus : 256);
   uint64_t offs[32];
   const uint64_t stride = wg_layout((int32_t)nmax, (int32_t)nnzmax, offs);
@@ -911,11 +924,13 @@ gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const i
     return GP_EDEVICE;
   if (ntot < 0) return GP_EINVAL;
   const int cus = b->cus > 0 ? b->cus : 256;
-  // persistent workgroups per compute unit x graphs per queue pop x queue order
+  // persistent workgroups per compute unit (two fit by LDS and registers) x
+  // graphs per queue pop x queue order (order 2 uses the timeline of the
+  // configuration run just before it)
   std::vector<int> cand;
-  for (int per_cu : {1, 2, 3})
+  for (int per_cu : {1, 2})
     for (int chunk : {1, 2, 4})
-      for (int order : {0, 1}) {
+      for (int order : {0, 1, 2}) {
         cand.push_back(per_cu * cus);
         cand.push_back(chunk);
         cand.push_back(order);
