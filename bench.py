@@ -413,7 +413,7 @@ def main():
                             "all_ok": all(r.status == 0 for r in resb),
                             "feasible": int(sum(r.feasible for r in resb)),
                             "autotuned": {"workgroups": chosen[0], "chunk": chosen[1],
-                                          "order_mode": chosen[2],
+                                          "order_mode": chosen[2], "team_width_shift": chosen[3],
                                           "tuning_ms_per_call": round(tune_ms, 3)}}
         out["batch4096"]["timeline"] = batch_timeline(bt, bb, chosen)
         gotb = pb.cpu().numpy()

@@ -267,6 +267,10 @@ gp_status gp_batch_create(gp_batch** b, void* stream);
  * size on b first (largest first without one).  None of them changes any
  * result. */
 gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode);
+/* Lanes per row of the batched kernels: the degree-based choice (4 to 64)
+ * scaled by 2^shift and kept within [4, 64], shift in [-4, 1] (default 0).
+ * No result depends on it; it is a tuning knob of the autotuner. */
+gp_status gp_batch_team_width(gp_batch* b, int32_t shift);
 gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
                              const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,
                              const int64_t* vwgt, const gp_options* o, int8_t* part,
@@ -302,12 +306,14 @@ gp_status gp_partition_batch_noalloc(int32_t G, const int64_t* voff, const int64
 /* Autotuner of the batched path: runs gp_partition_batch with each of 18
  * configurations (1 or 2 persistent workgroups per compute unit x 1, 2 or 4
  * graphs per queue pop x largest-first, input or previous-longest-first
- * order), checks that
- * every configuration returns byte-identical part and res, times `reps`
- * calls of each (host wall clock, whole calls), and keeps the fastest in b
- * for later calls.  chosen (host int32[3], may be NULL) receives workgroups,
- * chunk, order_mode; ms (may be NULL) its mean time per call.  part and res
- * hold the result on return.  GP_EDEVICE if two configurations disagree (the
+ * order), then the fastest of them with the team width divided by 16, 8, 4
+ * and 2, and doubled (gp_batch_team_width), checks that every configuration
+ * returns
+ * byte-identical part and res, times `reps` calls of each (host wall clock,
+ * whole calls), and keeps the fastest in b for later calls.  chosen (host
+ * int32[4], may be NULL) receives workgroups, chunk, order_mode and the team
+ * width shift; ms (may be NULL) its mean time per call.  part and res hold
+ * the result on return.  GP_EDEVICE if two configurations disagree (the
  * previous configuration is then restored). */
 gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const int64_t* eoff,
                             const int32_t* xadj, const int32_t* adjncy, const int64_t* adjwgt,

@@ -127,6 +127,8 @@ def _load():
     lib.gp_profile_read.restype = i32
     lib.gp_batch_create.argtypes = [ctypes.POINTER(vp), vp]
     lib.gp_batch_create.restype = ctypes.c_int
+    lib.gp_batch_team_width.argtypes = [vp, i32]
+    lib.gp_batch_team_width.restype = ctypes.c_int
     lib.gp_batch_timeline.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
     lib.gp_batch_timeline.restype = ctypes.c_int
     lib.gp_batch_config.argtypes = [vp, i32, i32, i32]
@@ -425,6 +427,11 @@ class Batch:
         if st != OK:
             raise GPError(st, "gp_batch_export")
 
+    def team_width(self, shift: int):
+        st = _lib.gp_batch_team_width(self._h, int(shift))
+        if st != OK:
+            raise GPError(st, "gp_batch_team_width")
+
     def timeline(self, G: int):
         """(ticks int64[G, 2]: start / end of each graph of the last call, clock rate in Hz)."""
         t = np.zeros((max(int(G), 1), 2), np.int64)
@@ -457,21 +464,22 @@ class Batch:
 
     def autotune(self, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, opts=None, part=None,
                  reps: int = 3):
-        """gp_batch_autotune: returns (part, results, (workgroups, chunk, order_mode), ms)."""
+        """gp_batch_autotune: returns (part, results, (workgroups, chunk, order_mode,
+        team width shift), ms)."""
         import torch
         opts = opts or options()
         if part is None:
             part = torch.empty(max(int(vwgt.numel()) // 2, 1), dtype=torch.int8,
                                device=xadj.device)
         res = (Result * max(G, 1))()
-        chosen = (ctypes.c_int32 * 3)()
+        chosen = (ctypes.c_int32 * 4)()
         ms = ctypes.c_double(0)
         st = _lib.gp_batch_autotune(self._h, int(G), _ptr(voff), _ptr(eoff), _ptr(xadj),
                                     _ptr(adjncy), _ptr(adjwgt), _ptr(vwgt), ctypes.byref(opts),
                                     _ptr(part), res, int(reps), chosen, ctypes.byref(ms))
         if st != OK:
             raise GPError(st, "gp_batch_autotune")
-        return part, list(res[:G]), (chosen[0], chosen[1], chosen[2]), ms.value
+        return part, list(res[:G]), (chosen[0], chosen[1], chosen[2], chosen[3]), ms.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -97,6 +97,7 @@ struct BatchArgs {
   int32_t chunk;
   ExportArgs ex;  // ex.rec == nullptr: no export
   int64_t* tline; // per graph: wall-clock ticks when its workgroup took it and finished it
+  int32_t tw_shift;  // team width scale (see team_width_dev)
 };
 
 // per-workgroup scratch carved from wgs + blockIdx.x * wgs_stride
@@ -183,15 +184,18 @@ __device__ void* arena_alloc(const BatchArgs& a, uint64_t bytes) {
   return s_ptr;
 }
 
-__device__ int team_width_dev(int32_t n, int32_t nnz) {
-  // same thresholds as the single-graph path (avg degree 6, 12, 24, 48)
-  if (n <= 0) return 4;
+// lanes per row: the single-graph path's choice from the average degree
+// (thresholds 6, 12, 24, 48), scaled by 2^shift (a tuning knob of the batch;
+// no result depends on the team width), within [4, 64]
+__device__ int team_width_dev(int32_t n, int32_t nnz, int shift = 0) {
+  int tw = 64;
   const int64_t m = nnz;
-  if (m <= 6ll * n) return 4;
-  if (m <= 12ll * n) return 8;
-  if (m <= 24ll * n) return 16;
-  if (m <= 48ll * n) return 32;
-  return 64;
+  if (n <= 0 || m <= 6ll * n) tw = 4;
+  else if (m <= 12ll * n) tw = 8;
+  else if (m <= 24ll * n) tw = 16;
+  else if (m <= 48ll * n) tw = 32;
+  tw = shift >= 0 ? tw << shift : tw >> -shift;
+  return tw < 4 ? 4 : (tw > 64 ? 64 : tw);
 }
 
 #define TW_DISPATCH(tw, CALL)        \
@@ -335,7 +339,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.b = a.bal ? f.vg : f.vc;
     b_level_reset(ctrl, L > 0, 0, 1);
     __syncthreads();
-    const int tw = team_width_dev(f.n, f.nnz);
+    const int tw = team_width_dev(f.n, f.nnz, a.tw_shift);
     uint64_t hs = mix64(a.seed ^ (uint64_t)(uint32_t)L);
     for (int rr = 0; rr < a.R; rr++) {
       TW_DISPATCH(tw, (b_match_propose<TWv>(fv, match, sc.prop, ctrl, rr, hs, 0, 1)));
@@ -479,7 +483,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.adj = f.adj;
     fv.w = f.w;
     fv.b = a.bal ? f.vg : f.vc;
-    const int tw = team_width_dev(f.n, f.nnz);
+    const int tw = team_width_dev(f.n, f.nnz, a.tw_shift);
     for (int p = 0; p < a.P; p++) {
       TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, nullptr, 0, 1)));
       __syncthreads();
@@ -499,7 +503,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   v0w.b = a.bal ? l0.vg : l0.vc;
   b_clear_stats(ctrl, 0, 1);
   __syncthreads();
-  const int tw0 = team_width_dev(l0.n, l0.nnz);
+  const int tw0 = team_width_dev(l0.n, l0.nnz, a.tw_shift);
   TW_DISPATCH(tw0, (b_final_stats<TWv>(v0w, l0.vc, l0.vg, l0.part, ctrl, 0, 1)));
   __syncthreads();
   int8_t* out = a.part + v0;
@@ -600,6 +604,7 @@ struct gp_batch {
   int nwg = 0;          // persistent workgroups (0: 2 per compute unit)
   int chunk = 1;        // graphs per queue pop
   int order_mode = 0;   // 0: largest first, 1: input order, 2: previous call's longest first
+  int tw_shift = 0;     // team width scale, -4 to 1
   HBuf<unsigned char> wgs, arena;
   HBuf<int32_t> order;
   HBuf<int64_t> tline;  // per-graph start / end ticks of the last call
@@ -737,6 +742,12 @@ gp_status gp_batch_export(gp_batch* b, int64_t* rec, int32_t* xadj, int64_t* vwg
   return GP_OK;
 }
 
+gp_status gp_batch_team_width(gp_batch* b, int32_t shift) {
+  if (!b || shift < -4 || shift > 1) return GP_EINVAL;
+  b->tw_shift = shift;
+  return GP_OK;
+}
+
 gp_status gp_batch_config(gp_batch* b, int32_t workgroups, int32_t chunk, int32_t order_mode) {
   if (!b || workgroups < 0 || chunk < 1 || chunk > 64 || order_mode < 0 || order_mode > 2)
     return GP_EINVAL;
@@ -857,6 +868,7 @@ gp_status gp_partition_batch(gp_batch* b, int32_t G, const int64_t* voff, const 
   a.chunk = b->chunk;
   a.ex = b->ex;
   a.tline = b->tline.p;
+  a.tw_shift = b->tw_shift;
   b->tline_g = 0;
   if ((st = batch_launch(b, a, nwg)) != GP_OK) return st;
   if (hipMemcpyAsync(b->hres, b->res.p, sizeof(gp_result) * G, hipMemcpyDeviceToHost, s) !=
@@ -918,7 +930,7 @@ gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const i
   if (!b || reps < 1 || G < 0) return GP_EINVAL;
   if (G == 0) return gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part, res);
   if (!voff || !part || !res) return GP_EINVAL;
-  const int keep[3] = {b->nwg, b->chunk, b->order_mode};
+  const int keep[4] = {b->nwg, b->chunk, b->order_mode, b->tw_shift};
   int64_t ntot = 0;
   if (hipMemcpy(&ntot, voff + G, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
     return GP_EDEVICE;
@@ -926,25 +938,23 @@ gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const i
   const int cus = b->cus > 0 ? b->cus : 256;
   // persistent workgroups per compute unit (two fit by LDS and registers) x
   // graphs per queue pop x queue order (order 2 uses the timeline of the
-  // configuration run just before it)
+  // configuration run just before it); then the best of these with the team
+  // width divided by 16, 8, 4 and 2, and doubled
   std::vector<int> cand;
   for (int per_cu : {1, 2})
     for (int chunk : {1, 2, 4})
-      for (int order : {0, 1, 2}) {
-        cand.push_back(per_cu * cus);
-        cand.push_back(chunk);
-        cand.push_back(order);
-      }
-  const size_t nc = cand.size() / 3;
+      for (int order : {0, 1, 2}) cand.insert(cand.end(), {per_cu * cus, chunk, order, 0});
+  const size_t n1 = cand.size() / 4;
   std::vector<int8_t> ref_part((size_t)ntot), cur_part((size_t)ntot);
   std::vector<gp_result> ref_res((size_t)G), cur_res((size_t)G);
   double best = 1e300;
   size_t best_i = 0;
   gp_status st = GP_OK;
-  for (size_t i = 0; i < nc && st == GP_OK; i++) {
-    b->nwg = cand[3 * i];
-    b->chunk = cand[3 * i + 1];
-    b->order_mode = cand[3 * i + 2];
+  for (size_t i = 0; i < cand.size() / 4 && st == GP_OK; i++) {
+    b->nwg = cand[4 * i];
+    b->chunk = cand[4 * i + 1];
+    b->order_mode = cand[4 * i + 2];
+    b->tw_shift = cand[4 * i + 3];
     // the first call of a configuration captures its graph; it is not timed
     st = gp_partition_batch(b, G, voff, eoff, xadj, adjncy, adjwgt, vwgt, o, part,
                             i == 0 ? ref_res.data() : cur_res.data());
@@ -970,20 +980,26 @@ gp_status gp_batch_autotune(gp_batch* b, int32_t G, const int64_t* voff, const i
       best = t;
       best_i = i;
     }
+    if (i + 1 == n1)  // second stage: the team width of the best so far
+      for (int sh : {-4, -3, -2, -1, 1})
+        cand.insert(cand.end(), {cand[4 * best_i], cand[4 * best_i + 1], cand[4 * best_i + 2], sh});
   }
   if (st != GP_OK) {
     b->nwg = keep[0];
     b->chunk = keep[1];
     b->order_mode = keep[2];
+    b->tw_shift = keep[3];
     return st;
   }
-  b->nwg = cand[3 * best_i];
-  b->chunk = cand[3 * best_i + 1];
-  b->order_mode = cand[3 * best_i + 2];
+  b->nwg = cand[4 * best_i];
+  b->chunk = cand[4 * best_i + 1];
+  b->order_mode = cand[4 * best_i + 2];
+  b->tw_shift = cand[4 * best_i + 3];
   if (chosen) {
     chosen[0] = b->nwg;
     chosen[1] = b->chunk;
     chosen[2] = b->order_mode;
+    chosen[3] = b->tw_shift;
   }
   if (ms) *ms = best;
   // leave the caller the chosen configuration's (identical) outputs

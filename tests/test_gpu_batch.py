@@ -176,7 +176,8 @@ def test_batch_autotune_keeps_results(gp):
     say("case batch autotune")
     part, res, chosen, ms = bt.autotune(*dev, opts=gp.options(**kw), reps=1)
     say(f"chosen {chosen} {ms:.3f} ms")
-    assert chosen[1] in (1, 2, 4) and chosen[2] in (0, 1, 2) and chosen[0] > 0 and ms > 0
+    assert chosen[1] in (1, 2, 4) and chosen[2] in (0, 1, 2) and -4 <= chosen[3] <= 1
+    assert chosen[0] > 0 and ms > 0
     got = part.cpu().numpy()
     check_against_oracle(bb, graphs, got, res, kw)
     part2, res2 = bt.partition(*dev, opts=gp.options(**kw))
@@ -226,4 +227,28 @@ def test_batch_order_by_previous_times(gp):
         torch.cuda.synchronize()
         assert np.array_equal(p.cpu().numpy(), want)
         assert [x.as_dict() for x in r] == [x.as_dict() for x in r0]
+    b.close()
+
+
+@pytest.mark.parametrize("shift", [-4, -2, -1, 1])
+def test_batch_team_width_keeps_results(gp, shift):
+    """gp_batch_team_width changes the lanes per row, never a result."""
+    import torch
+    graphs = mixed_graphs(31, 40)
+    kw = dict(coarsen_to=48)
+    bb = dagen.concat(graphs)
+    dev = gp.batch_to_device(bb)
+    say(f"case batch team width {shift}")
+    ref = gp.Batch()
+    p0, r0 = ref.partition(*dev, opts=gp.options(**kw))
+    want = p0.cpu().numpy()
+    ref.close()
+    b = gp.Batch()
+    b.team_width(shift)
+    p, r = b.partition(*dev, opts=gp.options(**kw))
+    torch.cuda.synchronize()
+    assert np.array_equal(p.cpu().numpy(), want)
+    assert [x.as_dict() for x in r] == [x.as_dict() for x in r0]
+    with pytest.raises(gp.GPError):
+        b.team_width(2)
     b.close()
