@@ -307,10 +307,9 @@ gp_status gp_partition_batch_noalloc(int32_t G, const int64_t* voff, const int64
  * configurations (1 or 2 persistent workgroups per compute unit x 1, 2 or 4
  * graphs per queue pop x largest-first, input or previous-longest-first
  * order), then the fastest of them with the team width divided by 16, 8, 4
- * and 2, and doubled (gp_batch_team_width), checks that every configuration
- * returns
- * byte-identical part and res, times `reps` calls of each (host wall clock,
- * whole calls), and keeps the fastest in b for later calls.  chosen (host
+ * and 2, and doubled (gp_batch_team_width); checks that every configuration
+ * returns byte-identical part and res, times `reps` calls of each (host wall
+ * clock, whole calls), and keeps the fastest in b for later calls.  chosen (host
  * int32[4], may be NULL) receives workgroups, chunk, order_mode and the team
  * width shift; ms (may be NULL) its mean time per call.  part and res hold
  * the result on return.  GP_EDEVICE if two configurations disagree (the
