@@ -21,7 +21,10 @@ constexpr int kWaveCap = 512;     // longest candidate row sorted in LDS by one 
 constexpr int kRowBlockCap = 2048;  // longest candidate row sorted in LDS by one block (contraction)
 constexpr int kSortCap = 4096;    // longest candidate row sorted in LDS by one block
 constexpr int kWin = 4096;        // id window of the dense long-row merge
-constexpr int kLongCap = 4096;    // longest candidate row sorted by one wave (packed keys)
+constexpr int kLongCap = 4096;    // longest candidate row one wave can sort with packed keys
+// longest row given to one wave by the single-graph path (longer rows take a
+// block each: four waves per row beat one beyond it)
+constexpr int kLongWave = 2048;
 constexpr int kPackIdBits = 12;   // position bits of a packed key: kLongCap = 2^12
 constexpr int32_t kPackMaxNc = (1 << 19) - 1;  // coarse ids below this fit a packed key
 constexpr int kMaxLevels = 48;

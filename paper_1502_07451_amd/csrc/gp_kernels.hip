@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64) void k_contract_long(LevelView lv, const int32_
                                                       int32_t* tmpk, int64_t* tmpv, int32_t* cnt,
                                                       int64_t* tile_cnt,
                                                       const int32_t* longlist) {
-  __shared__ int32_t sk[kLongCap];
+  __shared__ int32_t sk[kLongWave];
   b_contract_longw(lv, cmap, cmem0, cmem1, toff, ctrl, tmpk, tmpv, cnt, tile_cnt, longlist, sk,
                    (int)blockIdx.x, (int)gridDim.x);
 }
@@ -636,11 +636,9 @@ bool launch_contract_b(const LevelView& lv, const int32_t* cmap, Ctrl* ctrl, con
   KCHECK();
   {
     ProfScope ps(PK_CONTRACT_LONG, 0, 0.0, s);
-    // rows of kWaveCap..kLongCap candidates, one wave each; ten waves fit a
-    // compute unit's LDS
-    // every coarse row may be long: up to one wave per row, at most the ten
-    // waves per compute unit that the LDS holds
-    const int gw = nc_max < 2560 ? (nc_max > 0 ? nc_max : 1) : 2560;
+    // rows of kWaveCap..kLongWave candidates, one wave each: up to one wave
+    // per row, at most the twenty waves per compute unit that the LDS holds
+    const int gw = nc_max < 5120 ? (nc_max > 0 ? nc_max : 1) : 5120;
     // (no tile counts: only the coarsest level's compaction needs them, and
     // it recounts them from the row lengths)
     k_contract_long<<<gw, 64, 0, s>>>(lv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw,

@@ -697,7 +697,7 @@ __device__ __forceinline__ void b_contract_rows(
       // rows beyond kWaveCap: one wave per row when the packed keys fit,
       // else one block per row; listed with one counter update per group
       const bool is_long =
-          in_rows && L > kWaveCap && (!hugelist || (L <= kLongCap && nc < kPackMaxNc));
+          in_rows && L > kWaveCap && (!hugelist || (L <= kLongWave && nc < kPackMaxNc));
       const bool is_huge = in_rows && L > kWaveCap && !is_long;
       const uint64_t ml = __ballot(is_long), mh = __ballot(is_huge);
       if (ml | mh) {
@@ -1075,8 +1075,8 @@ __device__ __forceinline__ int wave_row_packed(const LevelView& lv, const int32_
   return total;
 }
 
-// Rows of kWaveCap < L <= kLongCap candidates on a level with fewer than
-// kPackMaxNc coarse vertices: one wave per row (sk: the wave's kLongCap keys
+// Rows of kWaveCap < L <= kLongWave candidates on a level with fewer than
+// kPackMaxNc coarse vertices: one wave per row (sk: the wave's kLongWave keys
 // of LDS).
 __device__ __forceinline__ void b_contract_longw(LevelView lv, const int32_t* cmap,
                                                  const int32_t* cmem0, const int32_t* cmem1,
