@@ -341,11 +341,33 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     __syncthreads();
     const int tw = team_width_dev(f.n, f.nnz, a.tw_shift);
     uint64_t hs = mix64(a.seed ^ (uint64_t)(uint32_t)L);
-    for (int rr = 0; rr < a.R; rr++) {
-      TW_DISPATCH(tw, (b_match_propose<TWv>(fv, match, sc.prop, ctrl, rr, hs, 0, 1)));
-      __syncthreads();
-      b_match_resolve(f.n, match, sc.prop, ctrl, rr, 0, 1);
-      __syncthreads();
+    {
+      // Rounds as in the single-graph path, with one segment: round r >= 1
+      // first settles round r - 1 and lists the vertices still free, then
+      // only those propose.  Scratch idle during matching holds the free
+      // flags (the contraction's row offsets), the two lists and the second
+      // proposal buffer (its member arrays and row counts).
+      uint8_t* const fr = (uint8_t*)sc.toff;
+      int32_t* const lists[2] = {sc.cmem1, sc.cnt};
+      int32_t* const pa = sc.prop;
+      int32_t* const pb = sc.cmem0;
+      __shared__ int32_t s_lcnt[2];
+      for (int rr = 0; rr < a.R; rr++) {
+        int32_t* const cur = (rr & 1) ? pb : pa;
+        const int32_t* const prev = (rr & 1) ? pa : pb;
+        if (rr > 0) {
+          b_match_free(f.n, match, prev, fr, lists[(rr - 1) & 1], &s_lcnt[(rr - 1) & 1],
+                       lists[rr & 1], &s_lcnt[rr & 1], ctrl, rr, 0, 1);
+          __syncthreads();
+        }
+        TW_DISPATCH(tw, (b_match_round<TWv>(fv, match, fr, lists[rr & 1], &s_lcnt[rr & 1], prev,
+                                            cur, ctrl, rr, hs, 0, 1)));
+        __syncthreads();
+      }
+      if (a.R > 0) {
+        b_match_settle(f.n, match, ((a.R - 1) & 1) ? pb : pa, 0, 1);
+        __syncthreads();
+      }
     }
     if (a.R == 0) {
       for (int32_t u = threadIdx.x; u < f.n; u += blockDim.x) match[u] = -1;
@@ -368,11 +390,27 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,
                    sc.cmem1, sc.toff, ntiles, sc.tile_cnt, ntc, 0, 1);
     __syncthreads();
-    b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                    sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1);
-    __syncthreads();
+    // rows of at most 32 candidates by 32-lane teams with no barrier between
+    // rows; the longer ones are listed (in sc.prop, free after the two-hop
+    // pass) for the row sorts, then the longest for the block form
+    {
+      __shared__ int32_t s_ndefer;
+      __shared__ int64_t s_sio[2];
+      b_contract_short(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
+                       sc.prop, &s_ndefer, s_sio, 0, 1);
+      __syncthreads();
+      b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
+                      sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1, nullptr, sc.prop,
+                      &s_ndefer);
+      __syncthreads();
+    }
     b_contract_long(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                    sc.tile_cnt, sc.longlist, ntc, lds, false, 0, 1);
+                    nullptr, sc.longlist, ntc, lds, false, 0, 1, false);
+    __syncthreads();
+    // entry counts per coarse tile, then their scan (the compaction's bases)
+    b_tile_count(ctrl, sc.cnt, sc.tile_cnt, ntc, 0, 1);
+    __syncthreads();
+    b_tile_scan(ctrl, sc.tile_cnt, ntc);
     __syncthreads();
     b_contract_compact(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv, cxadj, cadj, cw, ntc,
                        0, 1);
@@ -471,9 +509,18 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     }
   }
   // ---- uncoarsening with refinement
+  // The first pass of a level reads the rows and keeps every vertex's
+  // external and internal weight; later passes scan those two arrays, which
+  // the moved vertices' rows bring up to date after each pass.  The arrays
+  // and the move marks reuse scratch that is idle by now (the contraction's
+  // row offsets and counts, the trials' incident totals).
+  int64_t* const sext = sc.toff;
+  int64_t* const sinn = ws.tot;
+  int32_t* const mark = sc.cnt;
+  __shared__ int64_t s_part[4];
   for (int l = L - 1; l >= 0; l--) {
     const LevelRec f = lev[l];
-    b_project(f.n, f.cmap, lev[l + 1].part, f.part, &ctrl->ref, a.P, 0, 1);
+    b_project(f.n, f.cmap, lev[l + 1].part, f.part, &ctrl->ref, a.P, 0, 1, mark);
     __syncthreads();
     LevelView fv;
     fv.n = f.n;
@@ -485,9 +532,19 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.b = a.bal ? f.vg : f.vc;
     const int tw = team_width_dev(f.n, f.nnz, a.tw_shift);
     for (int p = 0; p < a.P; p++) {
-      TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, nullptr, 0, 1)));
+      if (p == 0) {
+        TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, nullptr, 0, 1,
+                                            true, sext, sinn)));
+      } else {
+        b_refine_scan(f.n, f.part, fv.b, nullptr, sext, sinn, &ctrl->ref, sc.list, s_part, 0, 1);
+        __syncthreads();
+        b_refine_decide(f.n, &ctrl->ref, sc.list, s_part, 1, sel);
+      }
       __syncthreads();
-      b_refine_apply(f.part, &ctrl->ref, sc.list, ws.pass_sink, 0, 1);
+      b_refine_apply(f.part, &ctrl->ref, sc.list, ws.pass_sink, 0, 1, true, mark);
+      __syncthreads();
+      TW_DISPATCH(tw, (b_refine_delta<TWv>(fv, f.part, mark, sext, sinn, &ctrl->ref, sc.list, p,
+                                           0, 1)));
       __syncthreads();
     }
   }

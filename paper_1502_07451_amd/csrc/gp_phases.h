@@ -65,72 +65,9 @@ __device__ __forceinline__ bool match_better(int64_t w, int32_t v, int64_t bw, i
   return v < bv;
 }
 
-template <int TW>
-__device__ __forceinline__ void b_match_propose(LevelView lv, const int32_t* match,
-                                                          int32_t* prop, const Ctrl* ctrl,
-                                                          int round, uint64_t hs, int bid_, int nblk_) {
-  if (round > 0 && ctrl->made[round - 1] == 0) return;
-  const int64_t cap = ctrl->cap, maxb = ctrl->maxb;
-  const int lane = threadIdx.x & (TW - 1);
-  const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
-  const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
-  for (int64_t uu = team; uu < lv.n; uu += nteams) {
-    const int32_t u = (int32_t)uu;
-    if (round > 0 && match[u] != -1) continue;
-    const int64_t bu = lv.b[u];
-    const bool capcheck = bu + maxb > cap;
-    int64_t bw = -1;
-    int32_t bv = -1;
-    const int32_t e1 = lv.xend[u];
-    for (int32_t e = lv.xadj[u] + lane; e < e1; e += TW) {
-      const int32_t v = lv.adj[e];
-      if (round > 0 && match[v] != -1) continue;
-      if (capcheck && bu + lv.b[v] > cap) continue;
-      const int64_t w = lv.w[e];
-      if (match_better(w, v, bw, bv, hs, u)) {
-        bw = w;
-        bv = v;
-      }
-    }
-    butterfly<TW>([&](auto o) {
-      const int64_t ow = xor_lane<decltype(o)::value>(bw);
-      const int32_t ov = xor_lane<decltype(o)::value>(bv);
-      if (match_better(ow, ov, bw, bv, hs, u)) {
-        bw = ow;
-        bv = ov;
-      }
-    });
-    if (lane == 0) prop[u] = bv;
-  }
-}
-
-__device__ __forceinline__ void b_match_resolve(int32_t n, int32_t* match,
-                                                          const int32_t* prop, Ctrl* ctrl,
-                                                          int round, int bid_, int nblk_) {
-  if (round > 0 && ctrl->made[round - 1] == 0) return;
-  __shared__ int32_t sm[kBlock / 64];
-  int32_t made = 0;
-  for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
-       u += (int64_t)nblk_ * kBlock) {
-    if (round == 0) {
-      const int32_t p = prop[u];
-      const int32_t m = (p >= 0 && prop[p] == (int32_t)u) ? p : -1;
-      match[u] = m;
-      made += m >= 0;
-    } else if (match[u] == -1) {
-      const int32_t p = prop[u];
-      if (p >= 0 && prop[p] == (int32_t)u) {
-        match[u] = p;
-        made++;
-      }
-    }
-  }
-  made = block_sum<kBlock, int32_t>(made, sm);
-  if (threadIdx.x == 0 && made) atomicAdd(&ctrl->made[round], made);
-}
-
-// Matching rounds of the single-graph path.  Round r >= 1 runs in two
-// kernels: b_match_free settles the mutual proposals of round r - 1 and
+// Matching rounds.  Round r >= 1 runs in two steps (two kernels in the
+// single-graph path, one segment of one workgroup in the batched path):
+// b_match_free settles the mutual proposals of round r - 1 and
 // lists the vertices still free (fr[v] = 1 when match[v] is -1 afterwards),
 // then b_match_round proposes for the listed vertices only, among their free
 // neighbours, so the test of a neighbour is one byte gathered from an
@@ -868,6 +805,22 @@ __device__ __forceinline__ void b_contract_sums(Ctrl* ctrl, const int32_t* dcnt,
 
 // exclusive scan of the coarse-tile entry counts; their total is 2m of the
 // coarse level (one block)
+// per-tile entry counts of the coarse rows from their final counts (one
+// wave per tile of kTileC rows)
+__device__ __forceinline__ void b_tile_count(const Ctrl* ctrl, const int32_t* cnt,
+                                             int64_t* tile_cnt, int ntiles_c, int bid_,
+                                             int nblk_) {
+  static_assert(kTileC == 64, "one lane per row of a tile");
+  const int32_t nc = ctrl->nc;
+  for (int t = bid_ * (kBlock / 64) + (int)threadIdx.x / 64; t < ntiles_c;
+       t += nblk_ * (kBlock / 64)) {
+    const int32_t c = t * kTileC + lane_id();
+    int64_t k = c < nc ? cnt[c] : 0;
+    k = team_sum<64, int64_t>(k);
+    if (lane_id() == 0) tile_cnt[t] = k;
+  }
+}
+
 __device__ __forceinline__ void b_tile_scan(Ctrl* ctrl, int64_t* tile_cnt, int ntiles_c) {
   __shared__ int64_t sml[kBlock / 64];
   int64_t carry = 0;
