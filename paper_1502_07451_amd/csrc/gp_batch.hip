@@ -43,8 +43,9 @@ static_assert((size_t)kWin * 12 <= kBatchLds && (size_t)kRowBlockCap * 12 <= kBa
 
 struct LevelRec {
   int32_t n;
-  int32_t nnz;
+  int32_t nnz;      // entries in the rows
   const int32_t* xadj;
+  const int32_t* xend;  // row v is [xadj[v], xend[v]); coarse rows keep gaps
   const int32_t* adj;
   const int64_t* w;
   int64_t* vc;
@@ -307,6 +308,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     lev[0].n = n;
     lev[0].nnz = nnz;
     lev[0].xadj = xadj;
+    lev[0].xend = xadj + 1;
     lev[0].adj = adj0;
     lev[0].w = w0;
     lev[0].vc = vc0;
@@ -321,11 +323,12 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     int32_t* match = (int32_t*)arena_alloc(a, 4ull * f.n);
     int32_t* cmap = (int32_t*)arena_alloc(a, 4ull * f.n);
     int32_t* cxadj = (int32_t*)arena_alloc(a, 4ull * (f.n + 1));
+    int32_t* cxend = (int32_t*)arena_alloc(a, 4ull * f.n);
     int32_t* cadj = (int32_t*)arena_alloc(a, 4ull * f.nnz);
     int64_t* cw = (int64_t*)arena_alloc(a, 8ull * f.nnz);
     int64_t* cvc = (int64_t*)arena_alloc(a, 8ull * f.n);
     int64_t* cvg = (int64_t*)arena_alloc(a, 8ull * f.n);
-    if (!match || !cmap || !cxadj || !cadj || !cw || !cvc || !cvg) {
+    if (!match || !cmap || !cxadj || !cxend || !cadj || !cw || !cvc || !cvg) {
       oom = true;
       break;
     }
@@ -333,7 +336,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.n = f.n;
     fv.nnz = f.nnz;
     fv.xadj = f.xadj;
-    fv.xend = f.xadj + 1;
+    fv.xend = f.xend;
     fv.adj = f.adj;
     fv.w = f.w;
     fv.b = a.bal ? f.vg : f.vc;
@@ -390,30 +393,39 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     b_contract_map(fv, match, f.vc, f.vg, sc.tile_lead, sc.tile_ub, cmap, cvc, cvg, sc.cmem0,
                    sc.cmem1, sc.toff, ntiles, sc.tile_cnt, ntc, 0, 1);
     __syncthreads();
-    // rows of at most 32 candidates by 32-lane teams with no barrier between
-    // rows; the longer ones are listed (in sc.prop, free after the two-hop
-    // pass) for the row sorts, then the longest for the block form
+    // Every coarse row goes straight to its upper-bound offset toff[c] in
+    // the coarse arrays and keeps the gap after it (row c is [cxadj[c],
+    // cxend[c])).  Rows of at most 16 candidates are merged by 16-lane teams
+    // with no barrier between rows; the longer ones are listed (in sc.prop,
+    // free after the two-hop pass) for the row sorts, then the longest for
+    // the block form.
     {
       __shared__ int32_t s_ndefer;
       __shared__ int64_t s_sio[2];
-      b_contract_short(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                       sc.prop, &s_ndefer, s_sio, 0, 1);
+      b_contract_short<16>(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw, sc.cnt,
+                           sc.prop, &s_ndefer, s_sio, 0, 1);
       __syncthreads();
-      b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                      sc.tile_cnt, sc.longlist, ctrl, ntc, lds, 0, 1, nullptr, sc.prop,
-                      &s_ndefer);
+      b_contract_rows(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw, sc.cnt, sc.tile_cnt,
+                      sc.longlist, ctrl, ntc, lds, 0, 1, nullptr, sc.prop, &s_ndefer);
       __syncthreads();
     }
-    b_contract_long(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, sc.tmpk, sc.tmpv, sc.cnt,
-                    nullptr, sc.longlist, ntc, lds, false, 0, 1, false);
+    b_contract_long(fv, cmap, sc.cmem0, sc.cmem1, sc.toff, ctrl, cadj, cw, sc.cnt, nullptr,
+                    sc.longlist, ntc, lds, false, 0, 1, false);
     __syncthreads();
-    // entry counts per coarse tile, then their scan (the compaction's bases)
-    b_tile_count(ctrl, sc.cnt, sc.tile_cnt, ntc, 0, 1);
-    __syncthreads();
-    b_tile_scan(ctrl, sc.tile_cnt, ntc);
-    __syncthreads();
-    b_contract_compact(ctrl, sc.toff, sc.cnt, sc.tile_cnt, sc.tmpk, sc.tmpv, cxadj, cadj, cw, ntc,
-                       0, 1);
+    {
+      __shared__ int64_t s_tot[kBlock / 64];
+      const int32_t nc = ctrl->nc;
+      int64_t tot = 0;
+      for (int32_t c = threadIdx.x; c < nc; c += kBlock) {
+        const int64_t o = sc.toff[c];
+        const int32_t k = sc.cnt[c];
+        cxadj[c] = (int32_t)o;
+        cxend[c] = (int32_t)(o + k);
+        tot += k;
+      }
+      tot = block_sum<kBlock, int64_t>(tot, s_tot);
+      if (threadIdx.x == 0) ctrl->nnz_c = (int32_t)tot;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       lev[L].match = match;
@@ -422,6 +434,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
       c.n = ctrl->nc;
       c.nnz = ctrl->nnz_c;
       c.xadj = cxadj;
+      c.xend = cxend;
       c.adj = cadj;
       c.w = cw;
       c.vc = cvc;
@@ -431,6 +444,30 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     __syncthreads();
     L++;
     if (20 * (int64_t)lev[L].n > 19 * (int64_t)lev[L - 1].n || L == kMaxLevels) break;
+  }
+  // The coarsest level is made compact (n + 1 offsets) for the initial
+  // bisection: tile counts, their scan, the rows packed into sc.tmpk/tmpv
+  // from the offsets and counts the last contraction left in the scratch,
+  // then copied back.
+  if (L > 0 && !oom) {
+    const int ntc = (lev[L - 1].n + kTileC - 1) / kTileC;
+    LevelRec& cl = lev[L];
+    b_tile_count(ctrl, sc.cnt, sc.tile_cnt, ntc, 0, 1);
+    __syncthreads();
+    b_tile_scan(ctrl, sc.tile_cnt, ntc);
+    __syncthreads();
+    int32_t* cx = const_cast<int32_t*>(cl.xadj);
+    int32_t* ca = const_cast<int32_t*>(cl.adj);
+    int64_t* cw = const_cast<int64_t*>(cl.w);
+    b_contract_compact(ctrl, sc.toff, sc.cnt, sc.tile_cnt, ca, cw, cx, sc.tmpk, sc.tmpv, ntc, 0,
+                       1);
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < cl.nnz; q += kBlock) {
+      ca[q] = sc.tmpk[q];
+      cw[q] = sc.tmpv[q];
+    }
+    if (threadIdx.x == 0) cl.xend = cl.xadj + 1;
+    __syncthreads();
   }
   // assignment arrays of every level
   for (int l = 0; l <= L && !oom; l++) {
@@ -526,7 +563,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     fv.n = f.n;
     fv.nnz = f.nnz;
     fv.xadj = f.xadj;
-    fv.xend = f.xadj + 1;
+    fv.xend = f.xend;
     fv.adj = f.adj;
     fv.w = f.w;
     fv.b = a.bal ? f.vg : f.vc;

@@ -722,20 +722,21 @@ __device__ __forceinline__ void b_contract_rows(
   }
 }
 
-// Rows of at most 32 candidates, one 32-lane team each: the team reads its
-// row's members, gathers and sorts the candidates in registers and writes
+// Rows of at most T candidates, one T-lane team each (T = 32 in the
+// single-graph path; 16 in the batched path, whose one workgroup per graph
+// needs more rows in flight): the team reads its row's members, gathers and sorts the candidates in registers and writes
 // the merged row.  Block k takes the rows [kS, kS + S) (S = ceil(nc /
 // blocks)) and lists its longer rows at defer[kS ...], dcnt[k] of them,
 // for b_contract_rows (no global counter).  With few registers and no
 // barrier in the row loop, many rows' gather chains are in flight at once on
 // the large sparse levels.
+template <int T = 32>
 __device__ __forceinline__ void b_contract_short(LevelView lv, const int32_t* cmap,
                                                  const int32_t* cmem0, const int32_t* cmem1,
                                                  const int64_t* toff, const Ctrl* ctrl,
                                                  int32_t* okey, int64_t* oval, int32_t* cnt,
                                                  int32_t* defer, int32_t* dcnt, int64_t* sio,
                                                  int seg, int nseg) {
-  constexpr int T = 32;
   __shared__ int32_t s_nd;
   __shared__ int64_t sml[kBlock / 64];
   int64_t rin = 0, rout = 0;  // candidates read and entries written (lane 0 of each team)
