@@ -368,7 +368,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
         __syncthreads();
       }
       if (a.R > 0) {
-        b_match_settle(f.n, match, ((a.R - 1) & 1) ? pb : pa, 0, 1);
+        b_match_settle(f.n, match, ((a.R - 1) & 1) ? pb : pa, 0, 1, fr);
         __syncthreads();
       }
     }
@@ -376,9 +376,12 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
       for (int32_t u = threadIdx.x; u < f.n; u += blockDim.x) match[u] = -1;
       __syncthreads();
     }
-    TW_DISPATCH(tw, (b_hub<TWv>(fv, match, sc.prop, hs, 0, 1)));
+    // hub flags: the free flags, cleared by the settle (read every row
+    // without matching rounds)
+    uint8_t* const hflag = a.R > 0 ? (uint8_t*)sc.toff : nullptr;
+    TW_DISPATCH(tw, (b_hub<TWv>(fv, match, sc.prop, hs, 0, 1, hflag)));
     __syncthreads();
-    TW_DISPATCH(tw, (b_twohop<TWv>(fv, sc.prop, match, ctrl, 0, 1)));
+    TW_DISPATCH(tw, (b_twohop<TWv>(fv, sc.prop, match, ctrl, 0, 1, hflag)));
     __syncthreads();
     const int ntiles = (f.n + kTileV - 1) / kTileV;
     b_iso_count(fv, match, ctrl, sc.tile_lead, ntiles, 0, 1);

@@ -605,7 +605,8 @@ static gp_status run_partition_inner(gp_graph* g, const gp_options* o, int8_t* p
     LCHK(launch_match_rounds(fv, f->match.p, (uint8_t*)f->part.p, sc.cmem0, sc.cmem1,
                              (int32_t*)sc.partials, sc.prop, sc.longlist, g->ctrl, R, hs, tw,
                              s));
-    LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw, s));
+    LCHK(launch_twohop(fv, f->match.p, g->ctrl, sc, hs, tw,
+                       R > 0 ? (uint8_t*)f->part.p : nullptr, s));
     LCHK(launch_contract_a(fv, f->match.p, f->vc.p, f->vg.p, g->ctrl, sc, f->cmap.p, c->vc.p,
                            c->vg.p, s));
     LCHK(launch_contract_b(fv, f->cmap.p, g->ctrl, sc, f->n, c->xadj.p, c->xe.p, c->adj.p,

@@ -59,20 +59,21 @@ __global__ __launch_bounds__(kBlock) void k_match_free(int32_t n, int32_t* match
 }
 
 __global__ __launch_bounds__(kBlock) void k_match_settle(int32_t n, int32_t* match,
-                                                         const int32_t* prop) {
-  b_match_settle(n, match, prop, (int)blockIdx.x, (int)gridDim.x);
+                                                         const int32_t* prop, uint8_t* hflag) {
+  b_match_settle(n, match, prop, (int)blockIdx.x, (int)gridDim.x, hflag);
 }
 
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_hub(LevelView lv, const int32_t* match, int32_t* hub,
-                                                uint64_t hs) {
-  b_hub<TW>(lv, match, hub, hs, (int)blockIdx.x, (int)gridDim.x);
+                                                uint64_t hs, uint8_t* hflag) {
+  b_hub<TW>(lv, match, hub, hs, (int)blockIdx.x, (int)gridDim.x, hflag);
 }
 
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_twohop(LevelView lv, const int32_t* hub,
-                                                   int32_t* match, const Ctrl* ctrl) {
-  b_twohop<TW>(lv, hub, match, ctrl, (int)blockIdx.x, (int)gridDim.x);
+                                                   int32_t* match, const Ctrl* ctrl,
+                                                   const uint8_t* hflag) {
+  b_twohop<TW>(lv, hub, match, ctrl, (int)blockIdx.x, (int)gridDim.x, hflag);
 }
 
 __global__ __launch_bounds__(kBlock) void k_iso_count(LevelView lv, const int32_t* match,
@@ -525,8 +526,10 @@ bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32
   KCHECK();
   {
     ProfScope ps(PK_MATCH_SETTLE, 0, 0.0, s);
-    k_match_settle<<<grid_for(lv.n, kBlock * 4), kBlock, 0, s>>>(lv.n, match,
-                                                                  ((R - 1) & 1) ? prop_b : prop_a);
+    // the free flags are spent: the settle clears them as the two-hop
+    // pass's hub flags
+    k_match_settle<<<grid_for(lv.n, kBlock * 4), kBlock, 0, s>>>(
+        lv.n, match, ((R - 1) & 1) ? prop_b : prop_a, fr);
   }
   KCHECK();
   return true;
@@ -534,30 +537,30 @@ bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32
 
 template <int TW>
 static bool twohop_tw(const LevelView& lv, int32_t* match, int32_t* hub, const Ctrl* ctrl,
-                      uint64_t hs, hipStream_t s) {
+                      uint64_t hs, uint8_t* hflag, hipStream_t s) {
   const int grid = grid_for((int64_t)lv.n * TW, kBlock * 2);
   {
     ProfScope ps(PK_HUB, TW, 0.0, s);
-    k_hub<TW><<<grid, kBlock, 0, s>>>(lv, match, hub, hs);
+    k_hub<TW><<<grid, kBlock, 0, s>>>(lv, match, hub, hs, hflag);
   }
   KCHECK();
   {
     ProfScope ps(PK_TWOHOP, TW, 4.0 * (lv.n + 1) + 4.0 * lv.nnz + 4.0 * lv.n, s);
-    k_twohop<TW><<<grid, kBlock, 0, s>>>(lv, hub, match, ctrl);
+    k_twohop<TW><<<grid, kBlock, 0, s>>>(lv, hub, match, ctrl, hflag);
   }
   KCHECK();
   return true;
 }
 
 bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratch& sc,
-                   uint64_t hs, int tw, hipStream_t s) {
+                   uint64_t hs, int tw, uint8_t* hflag, hipStream_t s) {
   bool ok;
   switch (tw) {
-    case 4: ok = twohop_tw<4>(lv, match, sc.prop, ctrl, hs, s); break;
-    case 8: ok = twohop_tw<8>(lv, match, sc.prop, ctrl, hs, s); break;
-    case 16: ok = twohop_tw<16>(lv, match, sc.prop, ctrl, hs, s); break;
-    case 32: ok = twohop_tw<32>(lv, match, sc.prop, ctrl, hs, s); break;
-    default: ok = twohop_tw<64>(lv, match, sc.prop, ctrl, hs, s); break;
+    case 4: ok = twohop_tw<4>(lv, match, sc.prop, ctrl, hs, hflag, s); break;
+    case 8: ok = twohop_tw<8>(lv, match, sc.prop, ctrl, hs, hflag, s); break;
+    case 16: ok = twohop_tw<16>(lv, match, sc.prop, ctrl, hs, hflag, s); break;
+    case 32: ok = twohop_tw<32>(lv, match, sc.prop, ctrl, hs, hflag, s); break;
+    default: ok = twohop_tw<64>(lv, match, sc.prop, ctrl, hs, hflag, s); break;
   }
   if (!ok) return false;
   const int ntiles = (lv.n + kTileV - 1) / kTileV;

@@ -73,14 +73,18 @@ struct ProfScope {
 bool launch_level_reset(Ctrl* ctrl, int promote, hipStream_t s);
 // R matching rounds (from the second on, a settle of the previous round that
 // marks the free vertices in fr and lists them, then the proposals of the
-// listed vertices), then the last settled; fr: uint8[n] scratch; list_a /
+// listed vertices), then the last settled; fr: uint8[n] scratch, left
+// cleared by the last settle (the two-hop pass's hub flags); list_a /
 // list_b: two int32[n] lists; seg_cnt: int32[2 kMatchSegMax] list lengths;
 // prop_a / prop_b: two int32[n] proposal buffers
 bool launch_match_rounds(const LevelView& lv, int32_t* match, uint8_t* fr, int32_t* list_a,
                          int32_t* list_b, int32_t* seg_cnt, int32_t* prop_a, int32_t* prop_b,
                          Ctrl* ctrl, int R, uint64_t hs, int tw, hipStream_t s);
+// two-hop pass and isolated pairs; hflag: uint8[n] cleared flags (the
+// matching's fr after R >= 1 rounds) that let the pairing read only the rows
+// of hubs, or nullptr to read every row
 bool launch_twohop(const LevelView& lv, int32_t* match, Ctrl* ctrl, const Scratch& sc,
-                   uint64_t hs, int tw, hipStream_t s);
+                   uint64_t hs, int tw, uint8_t* hflag, hipStream_t s);
 bool launch_contract_a(const LevelView& lv, const int32_t* match, const int64_t* vc,
                        const int64_t* vg, Ctrl* ctrl, const Scratch& sc, int32_t* cmap,
                        int64_t* cvc, int64_t* cvg, hipStream_t s);

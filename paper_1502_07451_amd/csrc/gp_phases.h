@@ -201,11 +201,13 @@ __device__ __forceinline__ void b_match_round(LevelView lv, int32_t* match, cons
   }
 }
 
-// settles the mutual proposals of the last round
+// settles the mutual proposals of the last round; clears the hub flags of
+// the two-hop pass that follows (when given)
 __device__ __forceinline__ void b_match_settle(int32_t n, int32_t* match, const int32_t* prop,
-                                               int bid_, int nblk_) {
+                                               int bid_, int nblk_, uint8_t* hflag = nullptr) {
   for (int64_t u = (int64_t)bid_ * kBlock + threadIdx.x; u < n;
        u += (int64_t)nblk_ * kBlock) {
+    if (hflag) hflag[u] = 0;
     if (match[u] != -1) continue;
     const int32_t p = prop[u];
     if (p >= 0 && prop[p] == (int32_t)u) match[u] = p;
@@ -214,10 +216,12 @@ __device__ __forceinline__ void b_match_settle(int32_t n, int32_t* match, const 
 
 // --------------------------------------------------------------- two-hop pass
 // hub[u] = first neighbour of an unmatched u under the edge order (-1: none);
-// matched vertices get -2
+// matched vertices get -2.  hflag[h] = 1 marks every vertex that is some
+// vertex's hub (the flags were cleared by the settle before).
 template <int TW>
 __device__ __forceinline__ void b_hub(LevelView lv, const int32_t* match, int32_t* hub,
-                                                uint64_t hs, int bid_, int nblk_) {
+                                      uint64_t hs, int bid_, int nblk_,
+                                      uint8_t* hflag = nullptr) {
   const int lane = threadIdx.x & (TW - 1);
   const int64_t team = ((int64_t)bid_ * kBlock + threadIdx.x) / TW;
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
@@ -246,17 +250,23 @@ __device__ __forceinline__ void b_hub(LevelView lv, const int32_t* match, int32_
         bv = ov;
       }
     });
-    if (lane == 0) hub[u] = bv;
+    if (lane == 0) {
+      hub[u] = bv;
+      if (hflag && bv >= 0) hflag[bv] = 1;
+    }
   }
 }
 
 // The members of h's group are the x in row h with hub[x] == h; the sorted
 // row lists them in ascending id.  They are paired first-second,
 // third-fourth, ... when the pair fits under the cap.  Each unmatched vertex
-// has one hub, so every match[] entry is written by one team only.
+// has one hub, so every match[] entry is written by one team only.  A vertex
+// that is nobody's hub (hflag[h] == 0) has no members and pairs nothing, so
+// its row is not read.
 template <int TW>
-__device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub,
-                                                   int32_t* match, const Ctrl* ctrl, int bid_, int nblk_) {
+__device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub, int32_t* match,
+                                         const Ctrl* ctrl, int bid_, int nblk_,
+                                         const uint8_t* hflag = nullptr) {
   const int64_t cap = ctrl->cap;
   const int lane = threadIdx.x & (TW - 1);
   const int tb = lane_id() & ~(TW - 1);
@@ -266,6 +276,7 @@ __device__ __forceinline__ void b_twohop(LevelView lv, const int32_t* hub,
   const int64_t nteams = (int64_t)nblk_ * kBlock / TW;
   for (int64_t hh = team; hh < lv.n; hh += nteams) {
     const int32_t h = (int32_t)hh;
+    if (hflag && hflag[h] == 0) continue;  // the whole team skips together
     const int32_t e1 = lv.xend[h];
     int32_t pending = -1;
     for (int32_t e0 = lv.xadj[h]; e0 < e1; e0 += TW) {
