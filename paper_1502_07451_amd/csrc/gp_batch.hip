@@ -29,10 +29,13 @@ constexpr int kBatchLevels = kMaxLevels + 1;
 
 // dynamic LDS of the persistent kernel: the dense window of the long-row
 // merge (kWin x 12 bytes) and, in the same bytes, an LDS-resident trial of up
-// to kBatchTrialMax vertices.  48 KB plus the kernel's static LDS stay under
-// half of a compute unit's 160 KB, so two workgroups share each unit; larger
-// coarsest graphs take the global-memory trial form.
-constexpr size_t kBatchLds = 48 * 1024;
+// to kBatchTrialMax vertices (2,570).  58 KB plus the kernel's 19 KB of
+// static LDS stay under half of a compute unit's 160 KB, so two workgroups
+// share each unit, and the coarsest graphs of stalled coarsenings (tiled
+// Cholesky DAGs of 2,600 and 2,925 tasks stop at 2,150 and 2,432 vertices)
+// still fit; larger coarsest graphs take the global-memory trial form, which
+// rescans every vertex per pick (about ten times slower).
+constexpr size_t kBatchLds = 58 * 1024;
 constexpr int kBatchTrialMax =
     (int)((kBatchLds - trial_lds_bytes(0, kBlock)) / 23) < kTrialLdsMax
         ? (int)((kBatchLds - trial_lds_bytes(0, kBlock)) / 23)
