@@ -558,7 +558,7 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
   // and the move marks reuse scratch that is idle by now (the contraction's
   // row offsets and counts, the trials' incident totals).
   int64_t* const sext = sc.toff;
-  int64_t* const sinn = ws.tot;
+  int64_t* const stot = ws.tot;
   int32_t* const mark = sc.cnt;
   __shared__ int64_t s_part[4];
   for (int l = L - 1; l >= 0; l--) {
@@ -577,16 +577,16 @@ __device__ void batch_graph(const BatchArgs& a, int g, const WgScratch& ws, unsi
     for (int p = 0; p < a.P; p++) {
       if (p == 0) {
         TW_DISPATCH(tw, (b_refine_gain<TWv>(fv, f.part, &ctrl->ref, sc.list, sel, nullptr, 0, 1,
-                                            true, sext, sinn)));
+                                            true, sext, stot)));
       } else {
-        b_refine_scan(f.n, f.part, fv.b, nullptr, sext, sinn, &ctrl->ref, sc.list, s_part, 0, 1);
+        b_refine_scan(f.n, f.part, fv.b, nullptr, sext, stot, &ctrl->ref, sc.list, s_part, 0, 1);
         __syncthreads();
         b_refine_decide(f.n, &ctrl->ref, sc.list, s_part, 1, sel);
       }
       __syncthreads();
       b_refine_apply(f.part, &ctrl->ref, sc.list, ws.pass_sink, 0, 1, true, mark);
       __syncthreads();
-      TW_DISPATCH(tw, (b_refine_delta<TWv>(fv, f.part, mark, sext, sinn, &ctrl->ref, sc.list, p,
+      TW_DISPATCH(tw, (b_refine_delta<TWv>(fv, f.part, mark, sext, stot, &ctrl->ref, sc.list, p,
                                            0, 1)));
       __syncthreads();
     }

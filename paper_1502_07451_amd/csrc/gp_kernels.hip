@@ -229,27 +229,27 @@ template <int TW>
 __global__ __launch_bounds__(kBlock) void k_refine_gain(LevelView lv, const int8_t* part,
                                                         RefCtl* rc, Cand* list,
                                                         int64_t* partials, int64_t* sext,
-                                                        int64_t* sinn, const int64_t* b1) {
+                                                        int64_t* stot, const int64_t* b1) {
   __shared__ SelShared sel;
   b_refine_gain<TW>(lv, part, rc, list, &sel, partials, (int)blockIdx.x, (int)gridDim.x, false,
-                    sext, sinn, b1);
+                    sext, stot, b1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_scan(int32_t n, const int8_t* part,
                                                         const int64_t* b, const int64_t* b1,
-                                                        const int64_t* sext, const int64_t* sinn,
+                                                        const int64_t* sext, const int64_t* stot,
                                                         RefCtl* rc, Cand* list,
                                                         int64_t* partials) {
-  b_refine_scan(n, part, b, b1, sext, sinn, rc, list, partials, (int)blockIdx.x,
+  b_refine_scan(n, part, b, b1, sext, stot, rc, list, partials, (int)blockIdx.x,
                 (int)gridDim.x);
 }
 
 template <int TW>
 __global__ __launch_bounds__(kBlock) void k_refine_delta(LevelView lv, const int8_t* part,
                                                          const int32_t* mark, int64_t* sext,
-                                                         int64_t* sinn, const RefCtl* rc,
+                                                         int64_t* stot, const RefCtl* rc,
                                                          const Cand* list, int p) {
-  b_refine_delta<TW>(lv, part, mark, sext, sinn, rc, list, p, (int)blockIdx.x, (int)gridDim.x);
+  b_refine_delta<TW>(lv, part, mark, sext, stot, rc, list, p, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine_decide(int32_t n, RefCtl* rc, const Cand* list,

@@ -1208,7 +1208,7 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
                                                         int64_t* partials, int bid_, int nblk_,
                                                         bool inline_tail = true,
                                                         int64_t* sext = nullptr,
-                                                        int64_t* sinn = nullptr,
+                                                        int64_t* stot = nullptr,
                                                         const int64_t* b1 = nullptr) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
@@ -1263,7 +1263,7 @@ __device__ __forceinline__ void b_refine_gain(LevelView lv, const int8_t* part,
         ext_acc += ext;
         if (sext) {
           sext[v] = ext;
-          sinn[v] = in;
+          stot[v] = ext + in;
         }
         cand = pv == s && (mode == 1 || gain > 0);
         if (cand) {
@@ -1468,12 +1468,13 @@ __device__ __forceinline__ void b_start_level(RefCtl* rc, int npass, int bid_, i
   if (threadIdx.x == 0) start_level(rc, npass);
 }
 
-// Later passes of a level read the per-vertex external and internal
-// weights kept in sext / sinn instead of the rows: one vertex per thread,
-// the same candidates and per-block partials as the gain kernel.
+// Later passes of a level read the per-vertex external weight and total
+// incident weight kept in sext / stot (internal = total - external) instead
+// of the rows: one vertex per thread, the same candidates and per-block
+// partials as the gain kernel.
 __device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, const int64_t* b,
                                               const int64_t* b1, const int64_t* sext,
-                                              const int64_t* sinn, RefCtl* rc, Cand* list,
+                                              const int64_t* stot, RefCtl* rc, Cand* list,
                                               int64_t* partials, int bid_, int nblk_) {
   __shared__ int64_t sml[kBlock / 64];
   if (rc->done) return;
@@ -1490,7 +1491,7 @@ __device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, con
     c.pad = 0;
     if (v < n) {
       const int8_t pv = part[v];
-      const int64_t ext = sext[v], in = sinn[v], w0 = b[v], w1 = b1 ? b1[v] : w0;
+      const int64_t ext = sext[v], in = stot[v] - ext, w0 = b[v], w1 = b1 ? b1[v] : w0;
       const int64_t gain = ext - in;
       ext_acc += ext;
       cand = pv == s && (mode == 1 || gain > 0);
@@ -1520,15 +1521,16 @@ __device__ __forceinline__ void b_refine_scan(int32_t n, const int8_t* part, con
 
 // After pass p moved the vertices marked p + 1 (all from one side to d):
 // every unmoved neighbour x of a moved vertex u sees the edge change sides
-// (internal <-> external, exact integer atomics, so the order does not
-// matter); a moved u swaps its external and internal weights, except for
-// the edges to other moved vertices, which stay internal.  One team per
-// listed candidate; unmoved candidates are skipped.
+// (internal <-> external: one exact integer atomic on its external weight,
+// so the order does not matter; its total does not change); a moved u
+// swaps its external and internal weights, except for the edges to other
+// moved vertices, which stay internal.  One team per listed candidate;
+// unmoved candidates are skipped.
 template <int TW>
 __device__ __forceinline__ void b_refine_delta(LevelView lv, const int8_t* part,
-                                               const int32_t* mark, int64_t* sext, int64_t* sinn,
-                                               const RefCtl* rc, const Cand* list, int p,
-                                               int bid_, int nblk_) {
+                                               const int32_t* mark, int64_t* sext,
+                                               const int64_t* stot, const RefCtl* rc,
+                                               const Cand* list, int p, int bid_, int nblk_) {
   // pass p did not run, moved nothing, or was the level's last
   if (rc->pass != p + 1 || rc->last_moved_n == 0 || rc->done) return;
   const uint32_t nlist = rc->last_ncand;
@@ -1547,19 +1549,13 @@ __device__ __forceinline__ void b_refine_delta(LevelView lv, const int8_t* part,
       const int64_t w = lv.w[e];
       if (mark[x] == stamp) {
         corr += w;
-      } else if (part[x] == d) {
-        atomicAdd((unsigned long long*)&sext[x], (unsigned long long)(-w));
-        atomicAdd((unsigned long long*)&sinn[x], (unsigned long long)w);
       } else {
-        atomicAdd((unsigned long long*)&sext[x], (unsigned long long)w);
-        atomicAdd((unsigned long long*)&sinn[x], (unsigned long long)(-w));
+        atomicAdd((unsigned long long*)&sext[x], (unsigned long long)(part[x] == d ? -w : w));
       }
     }
     corr = team_sum<TW>(corr);
     if (lane == 0) {
-      const int64_t e0 = sext[u], i0 = sinn[u];
-      sext[u] = i0 - corr;
-      sinn[u] = e0 + corr;
+      sext[u] = stot[u] - sext[u] - corr;  // the old internal weight, less corr
     }
   }
 }
