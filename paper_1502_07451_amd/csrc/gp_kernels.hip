@@ -545,7 +545,9 @@ static bool twohop_tw(const LevelView& lv, int32_t* match, int32_t* hub, const C
   }
   KCHECK();
   {
-    ProfScope ps(PK_TWOHOP, TW, 4.0 * (lv.n + 1) + 4.0 * lv.nnz + 4.0 * lv.n, s);
+    // every row is read only without hub flags; with them, the rows read
+    // depend on the matching (no byte count)
+    ProfScope ps(PK_TWOHOP, TW, hflag ? 0.0 : 4.0 * (lv.n + 1) + 4.0 * lv.nnz + 4.0 * lv.n, s);
     k_twohop<TW><<<grid, kBlock, 0, s>>>(lv, hub, match, ctrl, hflag);
   }
   KCHECK();
